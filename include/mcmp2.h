@@ -1,0 +1,176 @@
+/*
+ * mcmp2.h -- C ABI of the MI355X implementation of the per-step hot path of
+ * stochastic four-component relativistic MP2 (Cruz, Garza, Yanai, Hirata,
+ * arXiv 2203.05632, Sec. III).
+ *
+ * One MC step evaluates the redundant-walker estimator (Eq. redundant)
+ *   I'_n = (1/mC2) sum_{p<q} f(r1p, r2p, r1q, r2q, tau) / (w(r1p,r2p) w(r1q,r2q) w(tau))
+ * of the 13-dimensional integral that the Laplace transform turns Eq. FinalMP2
+ * into.  Spinor values come from the basis expansion of Eq. (C); the integrand
+ * is built from the 4x4 Green's functions G+ / G- (Sec. III) as
+ *   f = -(1/2) (D - X) / (r12 r34),
+ *   D = Tr[G-(3,1) G+(1,3)] Tr[G-(4,2) G+(2,4)],
+ *   X = Tr[G-(3,1) G+(1,4) G-(4,2) G+(2,3)],
+ * with G-(x,y) = sum_i phi_i(x) phi_i(y)^dagger exp(+eps_i tau) and
+ * G+(x,y) = sum_a phi_a(x) phi_a(y)^dagger exp(-eps_a tau).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status codes: MCMP2_OK or a negative MCMP2_E*; mcmp2_last_error() then
+ *   returns a thread-local message.  Nothing throws across the ABI.
+ * - Host pointers are read during the call only (init copies them).
+ *   Device pointers are caller-owned device memory; the library uses them on
+ *   the context's HIP stream and never frees them.  Calls enqueue work and
+ *   return without synchronising the host, except mcmp2_init and
+ *   mcmp2_destroy.
+ * - Complex arrays are interleaved (re, im) doubles.
+ * - Spinor components are ordered (L alpha, L beta, S alpha, S beta).
+ *   The paper prints one coefficient set C^L for both spins; this library
+ *   takes one coefficient block per spin: coeffs[s][mu][k], s = 0 alpha,
+ *   1 beta, mu over the L primitives then the S primitives.
+ * - After MCMP2_EDEVICE the context must only be destroyed.
+ */
+#ifndef MCMP2_H
+#define MCMP2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcmp2_ctx mcmp2_ctx; /* opaque; owns all of its device memory */
+
+enum {
+    MCMP2_OK = 0,
+    MCMP2_EINVAL = -1, /* bad argument: shape, range or null pointer */
+    MCMP2_ENOMEM = -2, /* device allocation failed */
+    MCMP2_EDEVICE = -3, /* a HIP call failed */
+    MCMP2_ESTATE = -4  /* call not valid in the context's state (e.g. gradients not enabled) */
+};
+
+/* Operand precision of the spinor and Green's-function contractions.
+ * Exponential scalings, weights and all accumulations stay in FP64. */
+enum { MCMP2_FP64 = 0, MCMP2_FP32 = 1, MCMP2_BF16 = 2, MCMP2_FP16 = 3 };
+
+/* Molecule, weight function and basis (host memory, caller-owned, copied by init). */
+typedef struct {
+    int32_t n_nuc;
+    const double *nuc_xyz;    /* [n_nuc][3] nuclear positions, bohr */
+    const double *wfn;        /* [n_nuc][4] = c1, zeta1, c2, zeta2 of Eq. basisSet (Table 1 form) */
+    int32_t n_L, n_S;         /* Cartesian primitives of the large and small component sets */
+    const double *prim_xyz;   /* [n_L+n_S][3] centres, L set first */
+    const double *prim_exp;   /* [n_L+n_S] exponents (> 0) */
+    const int32_t *prim_lxyz; /* [n_L+n_S][3] Cartesian powers, each in 0..4 */
+    const double *prim_norm;  /* [n_L+n_S] normalisation constants */
+} mcmp2_basis;
+
+/*
+ * mcmp2_init -- build a context for one walker set (Sec. III).
+ *   basis      : see mcmp2_basis.
+ *   coeffs     : host, complex [2][n_L+n_S][n_occ+n_vir], Eq. (C) coefficients.
+ *   eps        : host, [n_occ+n_vir] spinor energies, occupied first.
+ *   m_pairs    : number of electron-pair walkers m (>= 2), Eq. redundant.
+ *   n_tau_max  : largest n_tau a step will be given (>= 1).
+ *   precision  : MCMP2_FP64 (others: MCMP2_EINVAL until implemented).
+ *   want_grad  : non-zero to allow gradient outputs in mcmp2_step.
+ *   hip_stream : hipStream_t to enqueue on (NULL = default stream).
+ *   out        : receives the context.
+ * lambda = 2 (eps_LUMO - eps_HOMO) (Eq. tauWeight and the rule after it) and
+ * N_g (Sec. III, evaluated analytically from two-centre s-Gaussian Coulomb
+ * integrals) are computed here and frozen.  All per-step buffers are
+ * allocated here; mcmp2_step allocates nothing.
+ * Errors: EINVAL (sizes, pointers, lambda <= 0), ENOMEM, EDEVICE.
+ */
+int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps, int32_t n_occ,
+               int32_t n_vir, int32_t m_pairs, int32_t n_tau_max, int32_t precision, int32_t want_grad,
+               void *hip_stream, mcmp2_ctx **out);
+
+/*
+ * mcmp2_step -- one evaluation of Eq. redundant at fixed walkers and tau.
+ *   walkers : device [m][2][3] positions (r1p, r2p), bohr.
+ *   tau     : device [n_tau] imaginary times (>= 0), 1 <= n_tau <= n_tau_max.
+ *   e2_out  : device [n_tau][3]: per tau, the direct part Re(-D/2 ...), the
+ *             exchange part Re(+X/2 ...) and their sum, each divided by
+ *             w_p w_q w(tau) and averaged over the mC2 pairs p < q.
+ *   grad_eps, grad_coeffs : must be NULL in this version (ESTATE otherwise).
+ * Errors: EINVAL (null pointers, n_tau out of range), ESTATE, EDEVICE.
+ */
+int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
+               double *grad_eps, double *grad_coeffs);
+
+/*
+ * mcmp2_pair_weights -- w(r1p, r2p) = g(r1p) g(r2p) / (N_g r12p) for every
+ * walker (Sec. III); the Metropolis chain needs it once at its start.
+ *   walkers : device [m][2][3];  w : device [m] output.
+ */
+int mcmp2_pair_weights(mcmp2_ctx *ctx, const double *walkers, double *w);
+
+/*
+ * mcmp2_metropolis -- one Metropolis proposal per walker pair (Sec. III).
+ * Both electrons of pair p move jointly, each coordinate by
+ * delta * (2u - 1); the move is accepted iff u_acc < w(new)/w(old).
+ * Uniforms come from Philox4x64-10 (Salmon et al., SC'11) with key
+ * (key0, key1) and counter (step, p, purpose, 0): words 0-3 of purpose 0 and
+ * words 0-1 of purpose 1 are the six displacement uniforms (r1 x,y,z then
+ * r2 x,y,z), word 2 of purpose 1 is u_acc; a word u maps to (u >> 11) 2^-53.
+ *   walkers    : device [m][2][3], updated in place.
+ *   w          : device [m] current pair weights, updated in place.
+ *   n_accepted : device int32, incremented by the number of accepted moves
+ *                (may be NULL).
+ * Errors: EINVAL (null pointers, delta not finite or <= 0), EDEVICE.
+ */
+int mcmp2_metropolis(mcmp2_ctx *ctx, double *walkers, double *w, uint64_t key0, uint64_t key1,
+                     uint64_t step, double delta, int32_t *n_accepted);
+
+/*
+ * mcmp2_sample_tau -- n_tau imaginary times by the inverse CDF of
+ * w(tau) = lambda exp(-lambda tau) (Sec. III): tau_t = -ln(1 - u_t) / lambda
+ * with u_t word 0 of Philox counter (step, t, 2, 0), key (key0, key1).
+ *   tau : device [n_tau] output.
+ */
+int mcmp2_sample_tau(mcmp2_ctx *ctx, uint64_t key0, uint64_t key1, uint64_t step, int32_t n_tau,
+                     double *tau);
+
+/*
+ * mcmp2_constants -- host copies of the frozen sampling constants.
+ *   lambda, n_g : host outputs (either may be NULL).
+ */
+int mcmp2_constants(const mcmp2_ctx *ctx, double *lambda, double *n_g);
+
+/*
+ * Kernel timing with HIP events recorded on the context's stream, for
+ * measurement harnesses.  mcmp2_profile_begin(ctx, mask, max_launches)
+ * starts recording a start/stop event pair around every launch of the
+ * kernels selected by `mask` (bit i = kernel id i below), for at most
+ * max_launches launches in total (later launches run untimed).
+ * mcmp2_profile_end synchronises the stream, writes per-kernel total
+ * milliseconds and launch counts into host arrays of length MCMP2_NKERNELS
+ * (either may be NULL) and stops recording.
+ * Errors: EINVAL (max_launches < 1), ESTATE (end without begin), ENOMEM, EDEVICE.
+ */
+enum {
+    MCMP2_K_WALKER_WEIGHTS = 0,
+    MCMP2_K_BASIS_VALUES = 1,
+    MCMP2_K_SPINOR_GEMM = 2,
+    MCMP2_K_TAU_PREP = 3,
+    MCMP2_K_GREEN_CONTRACT = 4,
+    MCMP2_K_REDUCE = 5,
+    MCMP2_K_METROPOLIS = 6,
+    MCMP2_K_SAMPLE_TAU = 7,
+    MCMP2_NKERNELS = 8
+};
+int mcmp2_profile_begin(mcmp2_ctx *ctx, uint32_t mask, int32_t max_launches);
+int mcmp2_profile_end(mcmp2_ctx *ctx, double *total_ms, int64_t *launches);
+
+/* Release the context and its device memory (synchronises its stream). NULL is ignored. */
+void mcmp2_destroy(mcmp2_ctx *ctx);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char *mcmp2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCMP2_H */

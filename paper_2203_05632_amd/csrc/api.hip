@@ -1,0 +1,391 @@
+// C ABI of libmcmp2 (declared in include/mcmp2.h): context set-up, the
+// per-step driver of the hot path and the sampler entry points.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace {
+thread_local char g_err[512] = "";
+
+// Two-centre Coulomb integral of unnormalised s Gaussians:
+// int int exp(-a|r1-A|^2) exp(-b|r2-B|^2) / r12 = 2 pi^(5/2)/(a b sqrt(a+b)) F0(ab/(a+b) R^2).
+double coulomb_ss(double a, double b, double R2) {
+    const double T = a * b / (a + b) * R2;
+    const double F0 = T < 1e-14 ? 1.0 - T / 3.0 : 0.5 * std::sqrt(M_PI / T) * std::erf(std::sqrt(T));
+    return 2.0 * std::pow(M_PI, 2.5) / (a * b * std::sqrt(a + b)) * F0;
+}
+
+double s_norm(double z) { return std::pow(2.0 * z / M_PI, 0.75); }
+
+template <class T>
+int dalloc(T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        set_error("hipMalloc of %zu bytes failed", n * sizeof(T));
+        return MCMP2_ENOMEM;
+    }
+    return MCMP2_OK;
+}
+
+void profiler_release(Profiler &p);
+void free_ctx(mcmp2_ctx *c) {
+    profiler_release(c->prof);
+    void *bufs[] = {c->nuc, c->gpar, c->pxyz, c->pexp, c->pnorm, c->plxyz, c->coef, c->eps, c->XT,
+                    c->hinv, c->psi, c->scale, c->wtau, c->tiles, c->partial};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete c;
+}
+}  // namespace
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return MCMP2_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return MCMP2_EDEVICE;
+}
+
+namespace {
+// Launch through `fn`, bracketed by an event pair when kernel `kid` is being timed.
+template <class F>
+int timed(mcmp2_ctx *c, int kid, const char *what, F fn) {
+    Profiler &p = c->prof;
+    const bool rec = (p.mask >> kid & 1u) && p.used < p.capacity;
+    if (rec) {
+        int rc = check_hip(hipEventRecord(p.ev[2 * p.used], c->stream), "hipEventRecord");
+        if (rc != MCMP2_OK) return rc;
+    }
+    int rc = check_hip(fn(), what);
+    if (rc != MCMP2_OK) return rc;
+    if (rec) {
+        rc = check_hip(hipEventRecord(p.ev[2 * p.used + 1], c->stream), "hipEventRecord");
+        if (rc != MCMP2_OK) return rc;
+        p.kid[p.used++] = kid;
+    }
+    return MCMP2_OK;
+}
+
+void profiler_release(Profiler &p) {
+    if (p.ev) {
+        for (int i = 0; i < 2 * p.capacity; ++i)
+            if (p.ev[i]) (void)hipEventDestroy(p.ev[i]);
+    }
+    delete[] p.ev;
+    delete[] p.kid;
+    p = Profiler();
+}
+}  // namespace
+
+#define TRY(x)                     \
+    do {                           \
+        int rc_ = (x);             \
+        if (rc_ != MCMP2_OK) {     \
+            free_ctx(c);           \
+            return rc_;            \
+        }                          \
+    } while (0)
+
+extern "C" const char *mcmp2_last_error(void) { return g_err; }
+
+extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps, int32_t n_occ,
+                          int32_t n_vir, int32_t m_pairs, int32_t n_tau_max, int32_t precision, int32_t want_grad,
+                          void *hip_stream, mcmp2_ctx **out) {
+    g_err[0] = '\0';
+    if (!out) {
+        set_error("out is NULL");
+        return MCMP2_EINVAL;
+    }
+    *out = nullptr;
+    if (!basis || !coeffs || !eps || !basis->nuc_xyz || !basis->wfn || !basis->prim_xyz || !basis->prim_exp ||
+        !basis->prim_lxyz || !basis->prim_norm) {
+        set_error("null input pointer");
+        return MCMP2_EINVAL;
+    }
+    if (basis->n_nuc < 1 || basis->n_L < 1 || basis->n_S < 0 || n_occ < 1 || n_vir < 1 || m_pairs < 2 ||
+        n_tau_max < 1) {
+        set_error("sizes out of range: n_nuc=%d n_L=%d n_S=%d n_occ=%d n_vir=%d m=%d n_tau_max=%d", basis->n_nuc,
+                  basis->n_L, basis->n_S, n_occ, n_vir, m_pairs, n_tau_max);
+        return MCMP2_EINVAL;
+    }
+    if (precision != MCMP2_FP64) {
+        set_error("precision %d not available (FP64 only)", precision);
+        return MCMP2_EINVAL;
+    }
+    if (want_grad) {
+        set_error("gradients are not available in this build");
+        return MCMP2_ESTATE;
+    }
+    const int nb = basis->n_L + basis->n_S;
+    for (int i = 0; i < nb; ++i) {
+        for (int d = 0; d < 3; ++d) {
+            int l = basis->prim_lxyz[3 * i + d];
+            if (l < 0 || l > 4) {
+                set_error("primitive %d: Cartesian power %d out of range 0..4", i, l);
+                return MCMP2_EINVAL;
+            }
+        }
+        if (!(basis->prim_exp[i] > 0.0)) {
+            set_error("primitive %d: exponent must be positive", i);
+            return MCMP2_EINVAL;
+        }
+    }
+    for (int I = 0; I < basis->n_nuc; ++I)
+        if (!(basis->wfn[4 * I + 1] > 0.0) || !(basis->wfn[4 * I + 3] > 0.0)) {
+            set_error("nucleus %d: weight-function exponents must be positive", I);
+            return MCMP2_EINVAL;
+        }
+    const int nsp = n_occ + n_vir;
+    double homo = eps[0], lumo = eps[n_occ];
+    for (int i = 0; i < n_occ; ++i) homo = std::max(homo, eps[i]);
+    for (int a = n_occ; a < nsp; ++a) lumo = std::min(lumo, eps[a]);
+    const double lambda = 2.0 * (lumo - homo);
+    if (!(lambda > 0.0)) {
+        set_error("lambda = 2 (eps_LUMO - eps_HOMO) = %g must be positive", lambda);
+        return MCMP2_EINVAL;
+    }
+
+    mcmp2_ctx *c = new (std::nothrow) mcmp2_ctx();
+    if (!c) {
+        set_error("host allocation failed");
+        return MCMP2_ENOMEM;
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        set_error("no HIP device");
+        delete c;
+        return MCMP2_EDEVICE;
+    }
+    c->stream = (hipStream_t)hip_stream;
+    c->n_nuc = basis->n_nuc;
+    c->nL = basis->n_L;
+    c->nS = basis->n_S;
+    c->nb = nb;
+    c->no = n_occ;
+    c->nv = n_vir;
+    c->nsp = nsp;
+    c->m = m_pairs;
+    c->m_pad = (m_pairs + kWalkerPad - 1) / kWalkerPad * kWalkerPad;
+    c->E = 2 * c->m_pad;
+    c->R = 8 * c->m_pad;
+    c->T = c->m_pad / kTileWalkers;
+    c->n_tp = c->T * (c->T + 1) / 2;
+    c->n_tau_max = n_tau_max;
+    c->precision = precision;
+    c->want_grad = want_grad;
+    c->lambda = lambda;
+
+    // N_g = sum over all pairs of weight-function Gaussians (Sec. III).
+    std::vector<double> gpar(4 * (size_t)c->n_nuc);
+    double Ng = 0.0;
+    for (int I = 0; I < c->n_nuc; ++I) {
+        const double *w = basis->wfn + 4 * I;
+        gpar[4 * I] = w[0] * s_norm(w[1]);
+        gpar[4 * I + 1] = w[1];
+        gpar[4 * I + 2] = w[2] * s_norm(w[3]);
+        gpar[4 * I + 3] = w[3];
+    }
+    for (int I = 0; I < c->n_nuc; ++I)
+        for (int ka = 0; ka < 2; ++ka)
+            for (int J = 0; J < c->n_nuc; ++J)
+                for (int kb = 0; kb < 2; ++kb) {
+                    const double *A = basis->nuc_xyz + 3 * I, *B = basis->nuc_xyz + 3 * J;
+                    double R2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                                (A[2] - B[2]) * (A[2] - B[2]);
+                    Ng += gpar[4 * I + 2 * ka] * gpar[4 * J + 2 * kb] *
+                          coulomb_ss(gpar[4 * I + 2 * ka + 1], gpar[4 * J + 2 * kb + 1], R2);
+                }
+    c->Ng = Ng;
+
+    std::vector<int> tiles;
+    tiles.reserve(2 * (size_t)c->n_tp);
+    for (int P = 0; P < c->T; ++P)
+        for (int Q = P; Q < c->T; ++Q) {
+            tiles.push_back(P);
+            tiles.push_back(Q);
+        }
+
+    TRY(dalloc(&c->nuc, 3 * (size_t)c->n_nuc));
+    TRY(dalloc(&c->gpar, 4 * (size_t)c->n_nuc));
+    TRY(dalloc(&c->pxyz, 3 * (size_t)nb));
+    TRY(dalloc(&c->pexp, (size_t)nb));
+    TRY(dalloc(&c->pnorm, (size_t)nb));
+    TRY(dalloc(&c->plxyz, 3 * (size_t)nb));
+    TRY(dalloc(&c->coef, 2 * 2 * (size_t)nb * nsp));
+    TRY(dalloc(&c->eps, (size_t)nsp));
+    TRY(dalloc(&c->XT, (size_t)nb * c->E));
+    TRY(dalloc(&c->hinv, (size_t)c->m_pad));
+    TRY(dalloc(&c->psi, 2 * (size_t)nsp * c->R));
+    TRY(dalloc(&c->scale, (size_t)n_tau_max * nsp));
+    TRY(dalloc(&c->wtau, (size_t)n_tau_max));
+    TRY(dalloc(&c->tiles, 2 * (size_t)c->n_tp));
+    TRY(dalloc(&c->partial, (size_t)n_tau_max * c->n_tp * 2));
+
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return check_hip(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy");
+    };
+    TRY(up(c->nuc, basis->nuc_xyz, 3 * sizeof(double) * c->n_nuc));
+    TRY(up(c->gpar, gpar.data(), gpar.size() * sizeof(double)));
+    TRY(up(c->pxyz, basis->prim_xyz, 3 * sizeof(double) * nb));
+    TRY(up(c->pexp, basis->prim_exp, sizeof(double) * nb));
+    TRY(up(c->pnorm, basis->prim_norm, sizeof(double) * nb));
+    TRY(up(c->plxyz, basis->prim_lxyz, 3 * sizeof(int) * nb));
+    TRY(up(c->coef, coeffs, 2 * 2 * sizeof(double) * (size_t)nb * nsp));
+    TRY(up(c->eps, eps, sizeof(double) * nsp));
+    TRY(up(c->tiles, tiles.data(), tiles.size() * sizeof(int)));
+    // padding rows / points stay zero for the lifetime of the context
+    TRY(check_hip(hipMemset(c->XT, 0, sizeof(double) * (size_t)nb * c->E), "hipMemset"));
+    TRY(check_hip(hipMemset(c->psi, 0, 2 * sizeof(double) * (size_t)nsp * c->R), "hipMemset"));
+    TRY(check_hip(hipMemset(c->hinv, 0, sizeof(double) * c->m_pad), "hipMemset"));
+    TRY(check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize"));
+    *out = c;
+    return MCMP2_OK;
+}
+
+extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
+                          double *grad_eps, double *grad_coeffs) {
+    if (!c || !walkers || !tau || !e2_out) {
+        set_error("null argument");
+        return MCMP2_EINVAL;
+    }
+    if (n_tau < 1 || n_tau > c->n_tau_max) {
+        set_error("n_tau=%d outside 1..%d", n_tau, c->n_tau_max);
+        return MCMP2_EINVAL;
+    }
+    if (grad_eps || grad_coeffs) {
+        set_error("gradient outputs requested but not available");
+        return MCMP2_ESTATE;
+    }
+    int rc;
+    if ((rc = timed(c, MCMP2_K_WALKER_WEIGHTS, "walker_weights",
+                    [&] { return launch_walker_weights(c, walkers, nullptr, c->hinv); })) != MCMP2_OK)
+        return rc;
+    if ((rc = timed(c, MCMP2_K_BASIS_VALUES, "basis_values", [&] { return launch_basis_values(c, walkers); })) !=
+        MCMP2_OK)
+        return rc;
+    if ((rc = timed(c, MCMP2_K_SPINOR_GEMM, "spinor_gemm", [&] { return launch_spinor_gemm(c); })) != MCMP2_OK)
+        return rc;
+    if ((rc = timed(c, MCMP2_K_TAU_PREP, "tau_prep", [&] { return launch_tau_prep(c, tau, n_tau); })) != MCMP2_OK)
+        return rc;
+    if ((rc = timed(c, MCMP2_K_GREEN_CONTRACT, "green_contract", [&] { return launch_green_contract(c, n_tau); })) !=
+        MCMP2_OK)
+        return rc;
+    return timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); });
+}
+
+extern "C" int mcmp2_pair_weights(mcmp2_ctx *c, const double *walkers, double *w) {
+    if (!c || !walkers || !w) {
+        set_error("null argument");
+        return MCMP2_EINVAL;
+    }
+    return check_hip(launch_walker_weights(c, walkers, w, nullptr), "walker_weights");
+}
+
+extern "C" int mcmp2_metropolis(mcmp2_ctx *c, double *walkers, double *w, uint64_t key0, uint64_t key1,
+                                uint64_t step, double delta, int32_t *n_accepted) {
+    if (!c || !walkers || !w) {
+        set_error("null argument");
+        return MCMP2_EINVAL;
+    }
+    if (!(delta > 0.0) || !std::isfinite(delta)) {
+        set_error("delta must be finite and positive");
+        return MCMP2_EINVAL;
+    }
+    return timed(c, MCMP2_K_METROPOLIS, "metropolis",
+                 [&] { return launch_metropolis(c, walkers, w, key0, key1, step, delta, n_accepted); });
+}
+
+extern "C" int mcmp2_sample_tau(mcmp2_ctx *c, uint64_t key0, uint64_t key1, uint64_t step, int32_t n_tau,
+                                double *tau) {
+    if (!c || !tau) {
+        set_error("null argument");
+        return MCMP2_EINVAL;
+    }
+    if (n_tau < 1) {
+        set_error("n_tau must be >= 1");
+        return MCMP2_EINVAL;
+    }
+    return timed(c, MCMP2_K_SAMPLE_TAU, "sample_tau", [&] { return launch_sample_tau(c, key0, key1, step, n_tau, tau); });
+}
+
+extern "C" int mcmp2_constants(const mcmp2_ctx *c, double *lambda, double *n_g) {
+    if (!c) {
+        set_error("null context");
+        return MCMP2_EINVAL;
+    }
+    if (lambda) *lambda = c->lambda;
+    if (n_g) *n_g = c->Ng;
+    return MCMP2_OK;
+}
+
+extern "C" int mcmp2_profile_begin(mcmp2_ctx *c, uint32_t mask, int32_t max_launches) {
+    if (!c || max_launches < 1) {
+        set_error("null context or max_launches < 1");
+        return MCMP2_EINVAL;
+    }
+    profiler_release(c->prof);
+    Profiler &p = c->prof;
+    p.ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches]();
+    p.kid = new (std::nothrow) int[max_launches];
+    if (!p.ev || !p.kid) {
+        profiler_release(p);
+        set_error("host allocation failed");
+        return MCMP2_ENOMEM;
+    }
+    p.capacity = max_launches;
+    for (int i = 0; i < 2 * max_launches; ++i) {
+        int rc = check_hip(hipEventCreate(&p.ev[i]), "hipEventCreate");
+        if (rc != MCMP2_OK) {
+            profiler_release(p);
+            return rc;
+        }
+    }
+    p.mask = mask;
+    p.used = 0;
+    return MCMP2_OK;
+}
+
+extern "C" int mcmp2_profile_end(mcmp2_ctx *c, double *total_ms, int64_t *launches) {
+    if (!c) {
+        set_error("null context");
+        return MCMP2_EINVAL;
+    }
+    Profiler &p = c->prof;
+    if (p.capacity == 0) {
+        set_error("mcmp2_profile_end without mcmp2_profile_begin");
+        return MCMP2_ESTATE;
+    }
+    int rc = check_hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    double ms[MCMP2_NKERNELS] = {0};
+    int64_t n[MCMP2_NKERNELS] = {0};
+    for (int i = 0; i < p.used && rc == MCMP2_OK; ++i) {
+        float t = 0.f;
+        rc = check_hip(hipEventElapsedTime(&t, p.ev[2 * i], p.ev[2 * i + 1]), "hipEventElapsedTime");
+        ms[p.kid[i]] += t;
+        n[p.kid[i]] += 1;
+    }
+    profiler_release(p);
+    if (rc != MCMP2_OK) return rc;
+    for (int k = 0; k < MCMP2_NKERNELS; ++k) {
+        if (total_ms) total_ms[k] = ms[k];
+        if (launches) launches[k] = n[k];
+    }
+    return MCMP2_OK;
+}
+
+extern "C" void mcmp2_destroy(mcmp2_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+}

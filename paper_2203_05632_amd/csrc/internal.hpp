@@ -1,0 +1,76 @@
+// Internal declarations shared by the translation units of libmcmp2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mcmp2.h"
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// Walker pairs are padded to a multiple of kWalkerPad so that the point
+// dimension (2 per pair) tiles by 16 and the row dimension (8 per pair:
+// 2 electrons x 4 spinor components) by 64.
+constexpr int kWalkerPad = 8;
+// Walker tile of the Green's-function kernel: 2 pairs = 16 rows.
+constexpr int kTileWalkers = 2;
+
+// Event-pair timing of selected kernels (mcmp2_profile_begin/end).
+struct Profiler {
+    uint32_t mask = 0;
+    int capacity = 0, used = 0;
+    hipEvent_t *ev = nullptr;  // [capacity][2]
+    int *kid = nullptr;        // [capacity]
+};
+
+struct mcmp2_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_nuc = 0, nL = 0, nS = 0, nb = 0;
+    int no = 0, nv = 0, nsp = 0;
+    int m = 0, m_pad = 0;
+    int E = 0;      // padded number of points, 2 * m_pad
+    int R = 0;      // padded number of spinor rows, 8 * m_pad; row = 8 p + 4 e + c
+    int T = 0;      // walker tiles, m_pad / kTileWalkers
+    int n_tp = 0;   // tile pairs P <= Q
+    int n_tau_max = 0;
+    int precision = MCMP2_FP64;
+    int want_grad = 0;
+    double lambda = 0.0, Ng = 0.0;
+
+    // device memory
+    double *nuc = nullptr;    // [n_nuc][3]
+    double *gpar = nullptr;   // [n_nuc][4] = c1 N(z1), z1, c2 N(z2), z2
+    double *pxyz = nullptr;   // [nb][3]
+    double *pexp = nullptr;   // [nb]
+    double *pnorm = nullptr;  // [nb]
+    int *plxyz = nullptr;     // [nb][3]
+    double *coef = nullptr;   // [2][nb][nsp] complex
+    double *eps = nullptr;    // [nsp]
+    double *XT = nullptr;     // [nb][E] basis values, point fastest
+    double *hinv = nullptr;   // [m_pad] N_g / (g(r1p) g(r2p))
+    double *psi = nullptr;    // [nsp][R] complex, row fastest
+    double *scale = nullptr;  // [n_tau_max][nsp] exp(+eps tau) occupied, exp(-eps tau) virtual
+    double *wtau = nullptr;   // [n_tau_max]
+    int *tiles = nullptr;     // [n_tp][2] (P, Q), P <= Q
+    double *partial = nullptr;  // [n_tau_max][n_tp][2] per tile pair (direct, exchange)
+
+    Profiler prof;
+};
+
+// error reporting (thread-local message)
+void set_error(const char *fmt, ...);
+int check_hip(hipError_t e, const char *what);
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_walker_weights(const mcmp2_ctx *c, const double *walkers, double *w, double *hinv);
+hipError_t launch_metropolis(const mcmp2_ctx *c, double *walkers, double *w, uint64_t key0,
+                             uint64_t key1, uint64_t step, double delta, int32_t *n_acc);
+hipError_t launch_sample_tau(const mcmp2_ctx *c, uint64_t key0, uint64_t key1, uint64_t step,
+                             int n_tau, double *tau);
+hipError_t launch_basis_values(const mcmp2_ctx *c, const double *walkers);
+hipError_t launch_spinor_gemm(const mcmp2_ctx *c);
+hipError_t launch_tau_prep(const mcmp2_ctx *c, const double *tau, int n_tau);
+hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau);
+hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);

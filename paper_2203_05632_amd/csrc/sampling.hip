@@ -1,0 +1,129 @@
+// Samplers and weights of the MC-MP2 estimator (Sec. III of the paper):
+// electron-pair weight w(r1, r2) = g(r1) g(r2) / (N_g r12) with g of
+// Eq. basisSet, Metropolis moves of the walker pairs, and inverse-CDF
+// sampling of tau from w(tau) = lambda exp(-lambda tau).
+//
+// Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with key
+// (key0, key1) and counter (step, index, purpose, 0).
+//
+// Floating-point contraction is disabled in this file so that the walker
+// positions r + delta (2u - 1) are reproduced bit for bit by any IEEE
+// evaluation of the same expression.
+#pragma clang fp contract(off)
+
+#include "internal.hpp"
+
+namespace {
+
+constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
+
+struct u64x4 {
+    uint64_t x[4];
+};
+
+__device__ inline u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                      uint64_t k1) {
+    uint64_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += kW0;
+            k1 += kW1;
+        }
+        uint64_t hi0 = __umul64hi(kM0, x0), lo0 = kM0 * x0;
+        uint64_t hi1 = __umul64hi(kM1, x2), lo1 = kM1 * x2;
+        uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+    }
+    return {{x0, x1, x2, x3}};
+}
+
+__device__ inline double to_unit(uint64_t u) { return (double)(u >> 11) * 0x1.0p-53; }
+
+// g(r) of Eq. basisSet; gpar[I] = (c1 N(z1), z1, c2 N(z2), z2).
+__device__ inline double g_value(double x, double y, double z, const double *nuc, const double *gpar, int n_nuc) {
+    double out = 0.0;
+    for (int I = 0; I < n_nuc; ++I) {
+        double dx = x - nuc[3 * I], dy = y - nuc[3 * I + 1], dz = z - nuc[3 * I + 2];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        out = out + gpar[4 * I] * exp(-gpar[4 * I + 1] * r2);
+        out = out + gpar[4 * I + 2] * exp(-gpar[4 * I + 3] * r2);
+    }
+    return out;
+}
+
+__device__ inline double dist(const double *a, const double *b) {
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// w[p] = g(r1) g(r2) / (N_g r12) and hinv[p] = N_g / (g(r1) g(r2)).
+__global__ void walker_weights_kernel(const double *__restrict__ walkers, int m, const double *__restrict__ nuc,
+                                      const double *__restrict__ gpar, int n_nuc, double Ng, double *w,
+                                      double *hinv) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    const double *r1 = walkers + 6 * p, *r2 = r1 + 3;
+    double g1 = g_value(r1[0], r1[1], r1[2], nuc, gpar, n_nuc);
+    double g2 = g_value(r2[0], r2[1], r2[2], nuc, gpar, n_nuc);
+    if (w) w[p] = (g1 * g2) / (Ng * dist(r1, r2));
+    if (hinv) hinv[p] = Ng / (g1 * g2);
+}
+
+__global__ void metropolis_kernel(double *__restrict__ walkers, double *__restrict__ w, int m,
+                                  const double *__restrict__ nuc, const double *__restrict__ gpar, int n_nuc,
+                                  double Ng, uint64_t key0, uint64_t key1, uint64_t step, double delta,
+                                  int32_t *n_acc) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    u64x4 a = philox4x64_10(step, (uint64_t)p, 0, 0, key0, key1);
+    u64x4 b = philox4x64_10(step, (uint64_t)p, 1, 0, key0, key1);
+    double u[6] = {to_unit(a.x[0]), to_unit(a.x[1]), to_unit(a.x[2]),
+                   to_unit(a.x[3]), to_unit(b.x[0]), to_unit(b.x[1])};
+    double trial[6];
+    for (int i = 0; i < 6; ++i) trial[i] = walkers[6 * p + i] + delta * (2.0 * u[i] - 1.0);
+    double g1 = g_value(trial[0], trial[1], trial[2], nuc, gpar, n_nuc);
+    double g2 = g_value(trial[3], trial[4], trial[5], nuc, gpar, n_nuc);
+    double wt = (g1 * g2) / (Ng * dist(trial, trial + 3));
+    if (to_unit(b.x[2]) < wt / w[p]) {
+        for (int i = 0; i < 6; ++i) walkers[6 * p + i] = trial[i];
+        w[p] = wt;
+        if (n_acc) atomicAdd(n_acc, 1);
+    }
+}
+
+__global__ void sample_tau_kernel(uint64_t key0, uint64_t key1, uint64_t step, int n_tau, double lambda,
+                                  double *tau) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tau) return;
+    u64x4 a = philox4x64_10(step, (uint64_t)t, 2, 0, key0, key1);
+    tau[t] = -log(1.0 - to_unit(a.x[0])) / lambda;
+}
+
+}  // namespace
+
+hipError_t launch_walker_weights(const mcmp2_ctx *c, const double *walkers, double *w, double *hinv) {
+    int nb = (c->m + 63) / 64;
+    walker_weights_kernel<<<nb, 64, 0, c->stream>>>(walkers, c->m, c->nuc, c->gpar, c->n_nuc, c->Ng, w, hinv);
+    return hipGetLastError();
+}
+
+hipError_t launch_metropolis(const mcmp2_ctx *c, double *walkers, double *w, uint64_t key0, uint64_t key1,
+                             uint64_t step, double delta, int32_t *n_acc) {
+    int nb = (c->m + 63) / 64;
+    metropolis_kernel<<<nb, 64, 0, c->stream>>>(walkers, w, c->m, c->nuc, c->gpar, c->n_nuc, c->Ng, key0, key1,
+                                                step, delta, n_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_tau(const mcmp2_ctx *c, uint64_t key0, uint64_t key1, uint64_t step, int n_tau,
+                             double *tau) {
+    sample_tau_kernel<<<(n_tau + 63) / 64, 64, 0, c->stream>>>(key0, key1, step, n_tau, c->lambda, tau);
+    return hipGetLastError();
+}

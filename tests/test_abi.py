@@ -1,0 +1,42 @@
+"""The C-ABI library loads and exports every function include/mcmp2.h
+declares (no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mcmp2.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcmp2_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    from paper_2203_05632_amd._lib import EXPORTS
+    assert sorted(EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2203_05632_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libmcmp2.so not built")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_last_error_is_callable_without_device():
+    from paper_2203_05632_amd import load
+    assert isinstance(load().mcmp2_last_error(), bytes)
+
+
+def test_init_rejects_bad_arguments_before_touching_device():
+    from paper_2203_05632_amd import load
+    lib = load()
+    out = ctypes.c_void_p()
+    rc = lib.mcmp2_init(None, None, None, 1, 1, 2, 1, 0, 0, None, ctypes.byref(out))
+    assert rc == -1 and b"null" in lib.mcmp2_last_error()
