@@ -114,9 +114,8 @@ def main():
     hist = torch.zeros((max(K, W), inp.n_tau, 3), dtype=torch.float64, device="cuda")
 
     def one(s, out):
-        ctx.metropolis(wk, w, key, s, delta, n_acc)
-        ctx.sample_tau(key, s, tau)
-        ctx.step(wk, tau, out)
+        ctx.advance(wk, w, key, s, delta, tau, n_acc)   # Metropolis move + tau samples (one launch)
+        ctx.step(wk, tau, out)                          # estimator of Eq. redundant
 
     for i in range(W):
         one(step, hist[i])

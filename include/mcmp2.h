@@ -133,6 +133,15 @@ int mcmp2_sample_tau(mcmp2_ctx *ctx, uint64_t key0, uint64_t key1, uint64_t step
                      double *tau);
 
 /*
+ * mcmp2_advance -- mcmp2_metropolis followed by mcmp2_sample_tau for the same
+ * (key, step), in one kernel launch: identical results to the two calls.
+ *   walkers, w, n_accepted : as in mcmp2_metropolis;  tau : device [n_tau] output.
+ * Errors: EINVAL (null pointers, delta not finite or <= 0, n_tau < 1), EDEVICE.
+ */
+int mcmp2_advance(mcmp2_ctx *ctx, double *walkers, double *w, uint64_t key0, uint64_t key1, uint64_t step,
+                  double delta, int32_t *n_accepted, int32_t n_tau, double *tau);
+
+/*
  * mcmp2_constants -- host copies of the frozen sampling constants.
  *   lambda, n_g : host outputs (either may be NULL).
  */
@@ -150,14 +159,14 @@ int mcmp2_constants(const mcmp2_ctx *ctx, double *lambda, double *n_g);
  * Errors: EINVAL (max_launches < 1), ESTATE (end without begin), ENOMEM, EDEVICE.
  */
 enum {
-    MCMP2_K_WALKER_WEIGHTS = 0,
-    MCMP2_K_BASIS_VALUES = 1,
-    MCMP2_K_SPINOR_GEMM = 2,
-    MCMP2_K_TAU_PREP = 3,
-    MCMP2_K_GREEN_CONTRACT = 4,
-    MCMP2_K_REDUCE = 5,
-    MCMP2_K_METROPOLIS = 6,
-    MCMP2_K_SAMPLE_TAU = 7,
+    MCMP2_K_WALKER_WEIGHTS = 0, /* mcmp2_pair_weights */
+    MCMP2_K_STEP_PREP = 1,      /* basis values, walker factors, tau scalings */
+    MCMP2_K_SPINOR_GEMM = 2,    /* Eq. (C) */
+    MCMP2_K_GREEN_CONTRACT = 3, /* G-/G+ and the pair contraction */
+    MCMP2_K_REDUCE = 4,         /* compensated pair sums */
+    MCMP2_K_METROPOLIS = 5,     /* mcmp2_metropolis */
+    MCMP2_K_SAMPLE_TAU = 6,     /* mcmp2_sample_tau */
+    MCMP2_K_ADVANCE = 7,        /* mcmp2_advance */
     MCMP2_NKERNELS = 8
 };
 int mcmp2_profile_begin(mcmp2_ctx *ctx, uint32_t mask, int32_t max_launches);

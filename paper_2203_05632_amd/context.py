@@ -114,6 +114,17 @@ class Context:
             int(key[0]), int(key[1]), int(step), float(delta),
             None if n_accepted is None else _dev(n_accepted, (1,), torch.int32, name="n_accepted")))
 
+    def advance(self, walkers: torch.Tensor, w: torch.Tensor, key, step: int, delta: float, tau: torch.Tensor,
+                n_accepted: torch.Tensor = None) -> torch.Tensor:
+        """Metropolis move and tau samples of MC step `step` in one launch."""
+        n = int(tau.shape[0])
+        check(self._lib.mcmp2_advance(
+            self._h, _dev(walkers, (self.m, 2, 3), name="walkers"), _dev(w, (self.m,), name="w"),
+            int(key[0]), int(key[1]), int(step), float(delta),
+            None if n_accepted is None else _dev(n_accepted, (1,), torch.int32, name="n_accepted"),
+            n, _dev(tau, (n,), name="tau")))
+        return tau
+
     def sample_tau(self, key, step: int, tau: torch.Tensor) -> torch.Tensor:
         n = int(tau.shape[0])
         check(self._lib.mcmp2_sample_tau(self._h, int(key[0]), int(key[1]), int(step), n,

@@ -37,8 +37,8 @@ int dalloc(T **p, size_t n) {
 void profiler_release(Profiler &p);
 void free_ctx(mcmp2_ctx *c) {
     profiler_release(c->prof);
-    void *bufs[] = {c->nuc, c->gpar, c->pxyz, c->pexp, c->pnorm, c->plxyz, c->coef, c->eps, c->XT,
-                    c->hinv, c->psi, c->scale, c->wtau, c->tiles, c->partial};
+    void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->psi,
+                    c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete c;
@@ -218,32 +218,44 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
 
     TRY(dalloc(&c->nuc, 3 * (size_t)c->n_nuc));
     TRY(dalloc(&c->gpar, 4 * (size_t)c->n_nuc));
-    TRY(dalloc(&c->pxyz, 3 * (size_t)nb));
-    TRY(dalloc(&c->pexp, (size_t)nb));
-    TRY(dalloc(&c->pnorm, (size_t)nb));
-    TRY(dalloc(&c->plxyz, 3 * (size_t)nb));
+    TRY(dalloc(&c->pgeo, 4 * (size_t)nb));
+    TRY(dalloc(&c->pnl, 2 * (size_t)nb));
     TRY(dalloc(&c->coef, 2 * 2 * (size_t)nb * nsp));
     TRY(dalloc(&c->eps, (size_t)nsp));
-    TRY(dalloc(&c->XT, (size_t)nb * c->E));
     TRY(dalloc(&c->hinv, (size_t)c->m_pad));
     TRY(dalloc(&c->psi, 2 * (size_t)nsp * c->R));
     TRY(dalloc(&c->scale, (size_t)n_tau_max * nsp));
     TRY(dalloc(&c->wtau, (size_t)n_tau_max));
+    std::vector<int> work;
+    // one block tile's psi rows: 8 kTileWalkers rows x n_sp complex FP64
+    build_green_work(c->T, 8.0 * kTileWalkers * 16.0 * nsp, work);
+    c->n_slots = 4 * (int)work.size();
     TRY(dalloc(&c->tiles, 2 * (size_t)c->n_tp));
-    TRY(dalloc(&c->partial, (size_t)n_tau_max * c->n_tp * 2));
+    TRY(dalloc(&c->work, work.size()));
+    TRY(dalloc(&c->partial, (size_t)n_tau_max * c->n_slots * 2));
+    TRY(dalloc(&c->XT, (size_t)nb * c->E));
 
     auto up = [&](void *dst, const void *src, size_t bytes) {
         return check_hip(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy");
     };
     TRY(up(c->nuc, basis->nuc_xyz, 3 * sizeof(double) * c->n_nuc));
     TRY(up(c->gpar, gpar.data(), gpar.size() * sizeof(double)));
-    TRY(up(c->pxyz, basis->prim_xyz, 3 * sizeof(double) * nb));
-    TRY(up(c->pexp, basis->prim_exp, sizeof(double) * nb));
-    TRY(up(c->pnorm, basis->prim_norm, sizeof(double) * nb));
-    TRY(up(c->plxyz, basis->prim_lxyz, 3 * sizeof(int) * nb));
+    // packed primitive records: (A, zeta) and (N, powers as int64 bits)
+    std::vector<double> geo(4 * (size_t)nb), nl(2 * (size_t)nb);
+    for (int i = 0; i < nb; ++i) {
+        for (int d = 0; d < 3; ++d) geo[4 * i + d] = basis->prim_xyz[3 * i + d];
+        geo[4 * i + 3] = basis->prim_exp[i];
+        nl[2 * i] = basis->prim_norm[i];
+        const int64_t packed = (int64_t)basis->prim_lxyz[3 * i] | ((int64_t)basis->prim_lxyz[3 * i + 1] << 8) |
+                               ((int64_t)basis->prim_lxyz[3 * i + 2] << 16);
+        std::memcpy(&nl[2 * i + 1], &packed, sizeof(double));
+    }
+    TRY(up(c->pgeo, geo.data(), geo.size() * sizeof(double)));
+    TRY(up(c->pnl, nl.data(), nl.size() * sizeof(double)));
     TRY(up(c->coef, coeffs, 2 * 2 * sizeof(double) * (size_t)nb * nsp));
     TRY(up(c->eps, eps, sizeof(double) * nsp));
     TRY(up(c->tiles, tiles.data(), tiles.size() * sizeof(int)));
+    TRY(up(c->work, work.data(), work.size() * sizeof(int)));
     // padding rows / points stay zero for the lifetime of the context
     TRY(check_hip(hipMemset(c->XT, 0, sizeof(double) * (size_t)nb * c->E), "hipMemset"));
     TRY(check_hip(hipMemset(c->psi, 0, 2 * sizeof(double) * (size_t)nsp * c->R), "hipMemset"));
@@ -268,15 +280,10 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
         return MCMP2_ESTATE;
     }
     int rc;
-    if ((rc = timed(c, MCMP2_K_WALKER_WEIGHTS, "walker_weights",
-                    [&] { return launch_walker_weights(c, walkers, nullptr, c->hinv); })) != MCMP2_OK)
-        return rc;
-    if ((rc = timed(c, MCMP2_K_BASIS_VALUES, "basis_values", [&] { return launch_basis_values(c, walkers); })) !=
+    if ((rc = timed(c, MCMP2_K_STEP_PREP, "step_prep", [&] { return launch_step_prep(c, walkers, tau, n_tau); })) !=
         MCMP2_OK)
         return rc;
     if ((rc = timed(c, MCMP2_K_SPINOR_GEMM, "spinor_gemm", [&] { return launch_spinor_gemm(c); })) != MCMP2_OK)
-        return rc;
-    if ((rc = timed(c, MCMP2_K_TAU_PREP, "tau_prep", [&] { return launch_tau_prep(c, tau, n_tau); })) != MCMP2_OK)
         return rc;
     if ((rc = timed(c, MCMP2_K_GREEN_CONTRACT, "green_contract", [&] { return launch_green_contract(c, n_tau); })) !=
         MCMP2_OK)
@@ -304,6 +311,24 @@ extern "C" int mcmp2_metropolis(mcmp2_ctx *c, double *walkers, double *w, uint64
     }
     return timed(c, MCMP2_K_METROPOLIS, "metropolis",
                  [&] { return launch_metropolis(c, walkers, w, key0, key1, step, delta, n_accepted); });
+}
+
+extern "C" int mcmp2_advance(mcmp2_ctx *c, double *walkers, double *w, uint64_t key0, uint64_t key1, uint64_t step,
+                             double delta, int32_t *n_accepted, int32_t n_tau, double *tau) {
+    if (!c || !walkers || !w || !tau) {
+        set_error("null argument");
+        return MCMP2_EINVAL;
+    }
+    if (!(delta > 0.0) || !std::isfinite(delta)) {
+        set_error("delta must be finite and positive");
+        return MCMP2_EINVAL;
+    }
+    if (n_tau < 1) {
+        set_error("n_tau must be >= 1");
+        return MCMP2_EINVAL;
+    }
+    return timed(c, MCMP2_K_ADVANCE, "advance",
+                 [&] { return launch_advance(c, walkers, w, key0, key1, step, delta, n_accepted, n_tau, tau); });
 }
 
 extern "C" int mcmp2_sample_tau(mcmp2_ctx *c, uint64_t key0, uint64_t key1, uint64_t step, int32_t n_tau,

@@ -7,32 +7,33 @@
 //   G(x, y) = sum_k s_k psi[k][x] conj(psi[k][y]).
 // Only the 8x8 blocks of walker pairs p < q enter the estimator, and
 // G(y, x) = G(x, y)^dagger, so the kernel walks the upper triangle of
-// 16x16-row tiles (2 walker pairs per tile side).  One wave owns one tile
-// pair and computes both G- and G+ for it on FP64 MFMA, complex as real
-// pairs: with psi_x = a + ib and psi_y = c + id,
+// 32x32-row block tiles (4 walker pairs per side).  A workgroup owns one block
+// tile and computes G- and G+ for up to four tau samples from a single pass
+// over the operands, on FP64 MFMA with complex numbers as real pairs: with
+// psi_x = a + ib and psi_y = c + id,
 //   Re G += a c + b d,   Im G += b c - a d.
-// The tile never leaves the chip: the wave stages it in LDS and contracts
-// the (up to) four walker pairs it covers,
+// The tile never leaves the chip: per tau each wave stages its 16x16 G- and
+// G+ sub-tiles in LDS and contracts the (up to) four walker pairs they cover,
 //   D = Tr[G-(3,1) G+(1,3)] Tr[G-(4,2) G+(2,4)],
 //   X = Tr[G-(3,1) G+(1,4) G-(4,2) G+(2,3)],
 // (1 = r1p, 2 = r2p, 3 = r1q, 4 = r2q; G(3,1) = G(1,3)^dagger), and weights
 // each pair by N_g^2 / (g(1) g(2) g(3) g(4) w(tau)) -- the 1/(r12 r34) of the
-// integrand cancels the 1/r of the two pair weights.  Per tile pair it
-// writes the direct part -Re(D)/2 and the exchange part +Re(X)/2; a second
-// kernel reduces them with compensated (Neumaier) summation in a fixed order.
+// integrand cancels the 1/r of the two pair weights.  Per wave it writes the
+// direct part -Re(D)/2 and the exchange part +Re(X)/2 summed over its pairs;
+// a second kernel reduces them with compensated (Neumaier) summation in a
+// fixed order, so results are bitwise reproducible.  (Folding that reduction
+// into the last block to finish was measured slower: the device-scope release
+// fence it needs writes back each XCD's L2 once per block.)
+//
+// Work order: workgroups are dispatched round-robin over the 8 XCDs, each
+// with its own L2.  The host builds the wave-slot list so that the tile pairs
+// an XCD receives come from compact bands of tile rows and columns whose psi
+// slices fit that XCD's L2 (build_green_work).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace {
-
-__global__ void tau_prep_kernel(const double *__restrict__ tau, const double *__restrict__ eps, int n_tau, int nsp,
-                                int no, double lambda, double *__restrict__ scale, double *__restrict__ wtau) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    int t = blockIdx.y;
-    if (t >= n_tau || k >= nsp) return;
-    double tv = tau[t];
-    scale[(size_t)t * nsp + k] = k < no ? exp(eps[k] * tv) : exp(-eps[k] * tv);
-    if (k == 0) wtau[t] = lambda * exp(-lambda * tv);
-}
 
 struct cplx {
     double re, im;
@@ -46,103 +47,9 @@ __device__ inline cplx shfl_xor_c(cplx a, int mask) {
     return {__shfl_xor(a.re, mask, 64), __shfl_xor(a.im, mask, 64)};
 }
 
-// Accumulate sum_k s_k psi[k][rp + i] conj(psi[k][rq + j]) for k in [k_lo, k_hi).
-__device__ inline void green_tile(const double2 *__restrict__ psi, const double *__restrict__ sc, int R, int rp,
-                                  int rq, int k_lo, int k_hi, int li, int lk, d4v &acc_re, d4v &acc_im) {
-    for (int k0 = k_lo; k0 < k_hi; k0 += 4) {
-        const int k = k0 + lk;
-        double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-        if (k < k_hi) {
-            const double s = sc[k];
-            const double2 x = psi[(size_t)k * R + rp + li];
-            const double2 y = psi[(size_t)k * R + rq + li];
-            a = x.x * s;
-            b = x.y * s;
-            c = y.x;
-            d = y.y;
-        }
-        acc_re = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, acc_re, 0, 0, 0);
-        acc_re = __builtin_amdgcn_mfma_f64_16x16x4f64(b, d, acc_re, 0, 0, 0);
-        acc_im = __builtin_amdgcn_mfma_f64_16x16x4f64(b, c, acc_im, 0, 0, 0);
-        acc_im = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, d, acc_im, 0, 0, 0);
-    }
-}
-
-__global__ __launch_bounds__(256) void green_contract_kernel(const double *__restrict__ psi_, const double *__restrict__ scale,
-                                                             const double *__restrict__ wtau,
-                                                             const double *__restrict__ hinv,
-                                                             const int *__restrict__ tiles, int n_tp, int R, int no,
-                                                             int nsp, int m, double *__restrict__ partial) {
-    __shared__ cplx lds[4][2][256];
-    const double2 *psi = reinterpret_cast<const double2 *>(psi_);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tp = blockIdx.x * 4 + wave;
-    const int t = blockIdx.y;
-    const bool active = tp < n_tp;
-    const int li = lane & 15, lk = lane >> 4;
-    const double *sc = scale + (size_t)t * nsp;
-
-    int P = 0, Q = 0;
-    if (active) {
-        P = tiles[2 * tp];
-        Q = tiles[2 * tp + 1];
-        const int rp = 16 * P, rq = 16 * Q;
-        d4v gm_re = {0, 0, 0, 0}, gm_im = {0, 0, 0, 0}, gp_re = {0, 0, 0, 0}, gp_im = {0, 0, 0, 0};
-        green_tile(psi, sc, R, rp, rq, 0, no, li, lk, gm_re, gm_im);
-        green_tile(psi, sc, R, rp, rq, no, nsp, li, lk, gp_re, gp_im);
-        for (int v = 0; v < 4; ++v) {
-            const int i = 4 * v + lk;  // MFMA f64 result row of element v
-            lds[wave][0][i * 16 + li] = {gm_re[v], gm_im[v]};
-            lds[wave][1][i * 16 + li] = {gp_re[v], gp_im[v]};
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-
-    // 16 lanes per walker pair: (pp, qq) = walker offsets in the tiles,
-    // (a, b) = 4x4 matrix indices of this lane.
-    const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
-    const int a = (lane & 15) >> 2, b = lane & 3;
-    const cplx *Gm = lds[wave][0];
-    const cplx *Gp = lds[wave][1];
-    // block (e, e') of the pair: rows 8 pp + 4 e + i, cols 8 qq + 4 e' + j
-#define GB(G, e, f, i, j) G[(8 * pp + 4 * (e) + (i)) * 16 + 8 * qq + 4 * (f) + (j)]
-    cplx t1 = cmulc(GB(Gm, 0, 0, a, b), GB(Gp, 0, 0, a, b));
-    cplx t2 = cmulc(GB(Gm, 1, 1, a, b), GB(Gp, 1, 1, a, b));
-    cplx m1 = {0.0, 0.0}, m2 = {0.0, 0.0};
-    for (int k = 0; k < 4; ++k) {
-        m1 = cadd(m1, cmulc(GB(Gm, 0, 0, k, a), GB(Gp, 0, 1, k, b)));  // [G-(1,3)^H G+(1,4)]_{ab}
-        m2 = cadd(m2, cmulc(GB(Gm, 1, 1, k, b), GB(Gp, 1, 0, k, a)));  // [G-(2,4)^H G+(2,3)]_{ba}
-    }
-#undef GB
-    cplx xt = cmul(m1, m2);
-    for (int mask = 8; mask >= 1; mask >>= 1) {
-        t1 = cadd(t1, shfl_xor_c(t1, mask));
-        t2 = cadd(t2, shfl_xor_c(t2, mask));
-        xt = cadd(xt, shfl_xor_c(xt, mask));
-    }
-    const int p = kTileWalkers * P + pp, q = kTileWalkers * Q + qq;
-    double dir = 0.0, exc = 0.0;
-    if (p < q && q < m) {
-        const double W = hinv[p] * hinv[q] / wtau[t];
-        const cplx D = cmul(t1, t2);
-        dir = -0.5 * D.re * W;
-        exc = 0.5 * xt.re * W;
-    }
-    // pairs of this wave summed in a fixed order (lanes 0, 16, 32, 48)
-    double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64), d3 = __shfl(dir, 48, 64);
-    double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64), x3 = __shfl(exc, 48, 64);
-    if (lane == 0) {
-        double *out = partial + ((size_t)t * n_tp + tp) * 2;
-        out[0] = ((d0 + d1) + d2) + d3;
-        out[1] = ((x0 + x1) + x2) + x3;
-    }
-}
-
 // Neumaier (improved Kahan) summation: s + c carries the running total.
 __device__ inline void neumaier_add(double &s, double &c, double x) {
-    double t = s + x;
+    const double t = s + x;
     if (fabs(s) >= fabs(x))
         c += (s - t) + x;
     else
@@ -150,51 +57,303 @@ __device__ inline void neumaier_add(double &s, double &c, double x) {
     s = t;
 }
 
-// One block per tau: per-thread compensated sums over a fixed stride, then a
-// fixed-order compensated sum of the 256 thread totals by thread 0.
-__global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial, int n_tp, double inv_pairs,
-                                                     double *__restrict__ e2_out) {
-    __shared__ double sd[256], sx[256];
-    const int t = blockIdx.x;
-    const double *src = partial + (size_t)t * n_tp * 2;
+// Compensated sum over the n_slots partials of tau t by one block of 256
+// threads: per-thread sums over a fixed stride, then a fixed-shape tree
+// (wave shuffles, then the 4 wave totals in order) -- the same order in every
+// launch runs it, so the result is bitwise reproducible.
+__device__ inline void reduce_tau(const double *__restrict__ partial, int n_slots, int t, double inv_pairs,
+                                  double *__restrict__ e2_out, double (*sh)[4]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double *src = partial + (size_t)t * n_slots * 2;
     double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
-    for (int i = threadIdx.x; i < n_tp; i += 256) {
+    for (int i = threadIdx.x; i < n_slots; i += 256) {
         neumaier_add(s0, c0, src[2 * i]);
         neumaier_add(s1, c1, src[2 * i + 1]);
     }
-    sd[threadIdx.x] = s0 + c0;
-    sx[threadIdx.x] = s1 + c1;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double s0o = __shfl_down(s0, off, 64), c0o = __shfl_down(c0, off, 64);
+        const double s1o = __shfl_down(s1, off, 64), c1o = __shfl_down(c1, off, 64);
+        if (lane < off) {
+            neumaier_add(s0, c0, s0o);
+            c0 += c0o;
+            neumaier_add(s1, c1, s1o);
+            c1 += c1o;
+        }
+    }
+    if (lane == 0) {
+        sh[wave][0] = s0;
+        sh[wave][1] = c0;
+        sh[wave][2] = s1;
+        sh[wave][3] = c1;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a0 = 0.0, b0 = 0.0, a1 = 0.0, b1 = 0.0;
-        for (int i = 0; i < 256; ++i) {
-            neumaier_add(a0, b0, sd[i]);
-            neumaier_add(a1, b1, sx[i]);
+        double a0 = sh[0][0], b0 = sh[0][1], a1 = sh[0][2], b1 = sh[0][3];
+        for (int w = 1; w < 4; ++w) {
+            neumaier_add(a0, b0, sh[w][0]);
+            b0 += sh[w][1];
+            neumaier_add(a1, b1, sh[w][2]);
+            b1 += sh[w][3];
         }
         const double d = (a0 + b0) * inv_pairs, x = (a1 + b1) * inv_pairs;
         e2_out[3 * t] = d;
         e2_out[3 * t + 1] = x;
         e2_out[3 * t + 2] = d + x;
     }
+    __syncthreads();
+}
+
+// Block tile: 32 x 32 rows (4 walker pairs x 4 walker pairs), one 16 x 16
+// sub-tile per wave (wave w: rows 16 (w >> 1), cols 16 (w & 1)).  The K
+// dimension (spinors) is streamed in chunks of KC through double-buffered
+// LDS panels shared by the 4 waves: A = the 32 rows of the P range, B = the
+// 32 rows of the Q range, both [k][row] with the row fastest.
+constexpr int KC = 16;
+
+template <int NT>
+__device__ inline void mfma_kstep(const double2 *__restrict__ pa, const double2 *__restrict__ pb,
+                                  const double (&s)[NT], d4v (&acc_re)[NT], d4v (&acc_im)[NT]) {
+    const double2 x = *pa, y = *pb;
+    double a[NT], b[NT];
+    for (int t = 0; t < NT; ++t) {
+        a[t] = x.x * s[t];
+        b[t] = x.y * s[t];
+    }
+    for (int t = 0; t < NT; ++t) acc_re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], y.x, acc_re[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) acc_im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t], y.x, acc_im[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) acc_re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t], y.y, acc_re[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) acc_im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[t], y.y, acc_im[t], 0, 0, 0);
+}
+
+__device__ inline void chunk_load(const double2 *__restrict__ psi, int R, int rp, int rq, int kc, int k_hi, int e0,
+                                  int e1, double2 &ra0, double2 &ra1, double2 &rb0, double2 &rb1) {
+    const int k0 = kc + (e0 >> 5), k1 = kc + (e1 >> 5);
+    const size_t o0 = (size_t)k0 * R + (e0 & 31), o1 = (size_t)k1 * R + (e1 & 31);
+    const double2 z = {0.0, 0.0};
+    ra0 = k0 < k_hi ? psi[o0 + rp] : z;
+    rb0 = k0 < k_hi ? psi[o0 + rq] : z;
+    ra1 = k1 < k_hi ? psi[o1 + rp] : z;
+    rb1 = k1 < k_hi ? psi[o1 + rq] : z;
+}
+
+__device__ inline void chunk_store(double2 (*buf)[KC][32], int e0, int e1, const double2 &ra0, const double2 &ra1,
+                                   const double2 &rb0, const double2 &rb1) {
+    buf[0][e0 >> 5][e0 & 31] = ra0;
+    buf[1][e0 >> 5][e0 & 31] = rb0;
+    buf[0][e1 >> 5][e1 & 31] = ra1;
+    buf[1][e1 >> 5][e1 & 31] = rb1;
+}
+
+// tau scalings of one chunk: thread tid < 4 KC loads s_t[k] for t = tid / KC, k = kc + tid % KC
+__device__ inline double scale_load(const double *__restrict__ sc, int nsp, int nt, int kc, int k_hi, int tid) {
+    const int t = tid / KC, k = kc + tid % KC;
+    return (t < nt && k < k_hi) ? sc[(size_t)t * nsp + k] : 0.0;
+}
+
+// Stream spinors k in [k_lo, k_hi) through the LDS panels in chunks of KC
+// (the next chunk's global loads are in flight while the current one feeds
+// the MFMAs) and accumulate this wave's sub-tile for NT tau samples.
+template <int NT>
+__device__ inline void stream_k(const double2 *__restrict__ psi, const double *__restrict__ sc, int nsp, int R,
+                                int rp, int rq, int k_lo, int k_hi, double2 (*panel)[2][KC][32],
+                                double (*spanel)[4 * KC], d4v (&acc_re)[NT], d4v (&acc_im)[NT]) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wp = wave >> 1, wq = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    // Cooperative load of one chunk: thread element e in {tid, tid + 256} is
+    // (k = kc + e / 32, row = e % 32) of both panels; k >= k_hi reads as zero.
+    // (Plain scalars here: a lambda version over register arrays crashes the
+    // ROCm 7.2 AMDGPU backend in machine copy propagation.)
+    const int e0 = tid, e1 = tid + 256;
+    double2 ra0, ra1, rb0, rb1;
+    double sv;
+    const int n_chunks = (k_hi - k_lo + KC - 1) / KC;
+    chunk_load(psi, R, rp, rq, k_lo, k_hi, e0, e1, ra0, ra1, rb0, rb1);
+    sv = scale_load(sc, nsp, NT, k_lo, k_hi, tid);
+    chunk_store(panel[0], e0, e1, ra0, ra1, rb0, rb1);
+    if (tid < 4 * KC) spanel[0][tid] = sv;
+    __syncthreads();
+    for (int c = 0; c < n_chunks; ++c) {
+        const int buf = c & 1;
+        const int kc = k_lo + c * KC;
+        if (c + 1 < n_chunks) {
+            chunk_load(psi, R, rp, rq, kc + KC, k_hi, e0, e1, ra0, ra1, rb0, rb1);
+            sv = scale_load(sc, nsp, NT, kc + KC, k_hi, tid);
+        }
+        // operands of this chunk come from LDS only, so the next chunk's
+        // global loads stay in flight across all of its MFMAs
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 4) {
+            double s[NT];
+            for (int t = 0; t < NT; ++t) s[t] = spanel[buf][t * KC + ks + lk];
+            mfma_kstep<NT>(&panel[buf][0][ks + lk][16 * wp + li], &panel[buf][1][ks + lk][16 * wq + li], s, acc_re,
+                           acc_im);
+        }
+        if (c + 1 < n_chunks) {
+            chunk_store(panel[buf ^ 1], e0, e1, ra0, ra1, rb0, rb1);
+            if (tid < 4 * KC) spanel[buf ^ 1][tid] = sv;
+        }
+        __syncthreads();
+    }
+}
+
+// grid: n_slots / 4 blocks; tau samples t0 .. t0 + NT - 1.
+template <int NT>
+__global__ __launch_bounds__(256) void green_contract_kernel(
+    const double *__restrict__ psi_, const double *__restrict__ scale, const double *__restrict__ wtau,
+    const double *__restrict__ hinv, const int *__restrict__ tiles, const int *__restrict__ work, int n_slots, int R,
+    int no, int nsp, int m, int t0, double *__restrict__ partial) {
+    // 2 buffers x (A, B) x KC x 32 complex = 32 KB; reused for the G tiles of the epilogue
+    __shared__ double2 panel[2][2][KC][32];
+    __shared__ double spanel[2][4 * KC];  // tau scalings of the buffered chunks
+    const double2 *psi = reinterpret_cast<const double2 *>(psi_);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wp = wave >> 1, wq = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    const int item = work[blockIdx.x];
+    if (item < 0) {  // padding block: zero partials
+        for (int t = 0; t < NT; ++t)
+            if (lane == 0) {
+                double *out = partial + ((size_t)(t0 + t) * n_slots + 4 * blockIdx.x + wave) * 2;
+                out[0] = out[1] = 0.0;
+            }
+        return;
+    }
+    const int PT = tiles[2 * item], QT = tiles[2 * item + 1];
+    const int rp = 32 * PT, rq = 32 * QT;
+    const double *sc = scale + (size_t)t0 * nsp;
+
+    d4v gm_re[NT], gm_im[NT], gp_re[NT], gp_im[NT];
+    for (int t = 0; t < NT; ++t) gm_re[t] = gm_im[t] = gp_re[t] = gp_im[t] = d4v{0.0, 0.0, 0.0, 0.0};
+    // occupied spinors -> G-, then virtual spinors -> G+
+    stream_k<NT>(psi, sc, nsp, R, rp, rq, 0, no, panel, spanel, gm_re, gm_im);
+    stream_k<NT>(psi, sc, nsp, R, rp, rq, no, nsp, panel, spanel, gp_re, gp_im);
+
+    // epilogue: per tau, stage the wave's G- and G+ sub-tiles in LDS and contract
+    cplx *Gm = reinterpret_cast<cplx *>(&panel[0][0][0][0]) + wave * 512;
+    cplx *Gp = Gm + 256;
+    const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
+    const int a = (lane & 15) >> 2, b = lane & 3;
+    const int p = 4 * PT + 2 * wp + pp, q = 4 * QT + 2 * wq + qq;
+    const bool pair_ok = p < q && q < m;
+    const int slot = 4 * blockIdx.x + wave;
+    for (int t = 0; t < NT; ++t) {
+        for (int v = 0; v < 4; ++v) {
+            const int i = 4 * v + lk;  // MFMA f64 result row of element v
+            Gm[i * 16 + li] = {gm_re[t][v], gm_im[t][v]};
+            Gp[i * 16 + li] = {gp_re[t][v], gp_im[t][v]};
+        }
+        __syncthreads();
+        // block (e, f) of the pair: rows 8 pp + 4 e + i, cols 8 qq + 4 f + j
+#define GB(G, e, f, i, j) G[(8 * pp + 4 * (e) + (i)) * 16 + 8 * qq + 4 * (f) + (j)]
+        cplx t1 = cmulc(GB(Gm, 0, 0, a, b), GB(Gp, 0, 0, a, b));
+        cplx t2 = cmulc(GB(Gm, 1, 1, a, b), GB(Gp, 1, 1, a, b));
+        cplx m1 = {0.0, 0.0}, m2 = {0.0, 0.0};
+        for (int k = 0; k < 4; ++k) {
+            m1 = cadd(m1, cmulc(GB(Gm, 0, 0, k, a), GB(Gp, 0, 1, k, b)));  // [G-(1,3)^H G+(1,4)]_{ab}
+            m2 = cadd(m2, cmulc(GB(Gm, 1, 1, k, b), GB(Gp, 1, 0, k, a)));  // [G-(2,4)^H G+(2,3)]_{ba}
+        }
+#undef GB
+        cplx xt = cmul(m1, m2);
+        for (int mask = 8; mask >= 1; mask >>= 1) {
+            t1 = cadd(t1, shfl_xor_c(t1, mask));
+            t2 = cadd(t2, shfl_xor_c(t2, mask));
+            xt = cadd(xt, shfl_xor_c(xt, mask));
+        }
+        double dir = 0.0, exc = 0.0;
+        if (pair_ok) {
+            const double W = hinv[p] * hinv[q] / wtau[t0 + t];
+            const cplx D = cmul(t1, t2);
+            dir = -0.5 * D.re * W;
+            exc = 0.5 * xt.re * W;
+        }
+        // pairs of this wave summed in a fixed order (lanes 0, 16, 32, 48)
+        const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
+                     d3 = __shfl(dir, 48, 64);
+        const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
+                     x3 = __shfl(exc, 48, 64);
+        if (lane == 0) {
+            double *out = partial + ((size_t)(t0 + t) * n_slots + slot) * 2;
+            out[0] = ((d0 + d1) + d2) + d3;
+            out[1] = ((x0 + x1) + x2) + x3;
+        }
+        __syncthreads();  // the sub-tiles are rewritten for the next tau
+    }
+}
+
+// One block per tau sample.
+__global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial, int n_slots, double inv_pairs,
+                                                     double *__restrict__ e2_out) {
+    __shared__ double sh[4][4];
+    reduce_tau(partial, n_slots, blockIdx.x, inv_pairs, e2_out, sh);
 }
 
 }  // namespace
 
-hipError_t launch_tau_prep(const mcmp2_ctx *c, const double *tau, int n_tau) {
-    dim3 grid((c->nsp + 255) / 256, n_tau);
-    tau_prep_kernel<<<grid, 256, 0, c->stream>>>(tau, c->eps, n_tau, c->nsp, c->no, c->lambda, c->scale, c->wtau);
-    return hipGetLastError();
+// Tile pairs (P <= Q) of T block tiles are grouped into super-blocks of bands
+// of B tiles (I <= J) so that the psi rows of two bands (2 B tiles) fit in
+// ~2.5 MB of an XCD's 4 MB L2.  Super-blocks go to the 8 XCD lists largest
+// first to the least loaded list; the lists are padded to equal length (-1)
+// and interleaved so that workgroup b (dispatched to XCD b mod 8) takes entry
+// b / 8 of list b mod 8.
+void build_green_work(int T, double tile_bytes, std::vector<int> &work) {
+    constexpr int kXcd = 8;
+    int B = (int)std::max(1.0, 2.5e6 / (2.0 * tile_bytes));
+    B = std::min(B, T);
+    const int nbands = (T + B - 1) / B;
+    auto tp_index = [T](int P, int Q) { return P * T - P * (P - 1) / 2 + (Q - P); };
+    std::vector<std::vector<int>> blocks;
+    for (int I = 0; I < nbands; ++I)
+        for (int J = I; J < nbands; ++J) {
+            std::vector<int> items;
+            for (int P = I * B; P < std::min(T, (I + 1) * B); ++P)
+                for (int Q = std::max(P, J * B); Q < std::min(T, (J + 1) * B); ++Q) items.push_back(tp_index(P, Q));
+            if (!items.empty()) blocks.push_back(std::move(items));
+        }
+    std::stable_sort(blocks.begin(), blocks.end(),
+                     [](const std::vector<int> &x, const std::vector<int> &y) { return x.size() > y.size(); });
+    std::vector<std::vector<int>> lists(kXcd);
+    for (auto &blk : blocks) {
+        size_t best = 0;
+        for (size_t x = 1; x < lists.size(); ++x)
+            if (lists[x].size() < lists[best].size()) best = x;
+        lists[best].insert(lists[best].end(), blk.begin(), blk.end());
+    }
+    size_t len = 0;
+    for (auto &l : lists) len = std::max(len, l.size());
+    work.assign(kXcd * len, -1);
+    for (size_t b = 0; b < work.size(); ++b) {
+        const auto &l = lists[b % kXcd];
+        if (b / kXcd < l.size()) work[b] = l[b / kXcd];
+    }
 }
 
 hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau) {
-    dim3 grid((c->n_tp + 3) / 4, n_tau);
-    green_contract_kernel<<<grid, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->n_tp, c->R,
-                                                       c->no, c->nsp, c->m, c->partial);
-    return hipGetLastError();
+    const int nblocks = c->n_slots / 4;  // one work-list entry per block, four partial slots
+    for (int t0 = 0; t0 < n_tau; t0 += 4) {
+        const int nt = std::min(4, n_tau - t0);
+#define LAUNCH(NTV)                                                                                                  \
+    green_contract_kernel<NTV><<<nblocks, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv, c->tiles,        \
+                                                               c->work, c->n_slots, c->R, c->no, c->nsp, c->m, t0, \
+                                                               c->partial)
+        switch (nt) {
+            case 1: LAUNCH(1); break;
+            case 2: LAUNCH(2); break;
+            case 3: LAUNCH(3); break;
+            default: LAUNCH(4); break;
+        }
+#undef LAUNCH
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
+
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out) {
-    const double pairs = 0.5 * (double)c->m * (double)(c->m - 1);
-    reduce_kernel<<<n_tau, 256, 0, c->stream>>>(c->partial, c->n_tp, 1.0 / pairs, e2_out);
+    const double inv_pairs = 1.0 / (0.5 * (double)c->m * (double)(c->m - 1));
+    reduce_kernel<<<n_tau, 256, 0, c->stream>>>(c->partial, c->n_slots, inv_pairs, e2_out);
     return hipGetLastError();
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "mcmp2.h"
 
@@ -13,8 +14,8 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // dimension (2 per pair) tiles by 16 and the row dimension (8 per pair:
 // 2 electrons x 4 spinor components) by 64.
 constexpr int kWalkerPad = 8;
-// Walker tile of the Green's-function kernel: 2 pairs = 16 rows.
-constexpr int kTileWalkers = 2;
+// Block tile of the Green's-function kernel: 4 pairs = 32 rows.
+constexpr int kTileWalkers = 4;
 
 // Event-pair timing of selected kernels (mcmp2_profile_begin/end).
 struct Profiler {
@@ -42,22 +43,37 @@ struct mcmp2_ctx {
     // device memory
     double *nuc = nullptr;    // [n_nuc][3]
     double *gpar = nullptr;   // [n_nuc][4] = c1 N(z1), z1, c2 N(z2), z2
-    double *pxyz = nullptr;   // [nb][3]
-    double *pexp = nullptr;   // [nb]
-    double *pnorm = nullptr;  // [nb]
-    int *plxyz = nullptr;     // [nb][3]
+    double *pgeo = nullptr;   // [nb][4] centre x, y, z, exponent
+    double *pnl = nullptr;    // [nb][2] normalisation, Cartesian powers lx | ly << 8 | lz << 16 (int64 bits)
     double *coef = nullptr;   // [2][nb][nsp] complex
     double *eps = nullptr;    // [nsp]
-    double *XT = nullptr;     // [nb][E] basis values, point fastest
+    double *XT = nullptr;     // [nb][E] basis values, point fastest (padding points stay zero)
     double *hinv = nullptr;   // [m_pad] N_g / (g(r1p) g(r2p))
     double *psi = nullptr;    // [nsp][R] complex, row fastest
     double *scale = nullptr;  // [n_tau_max][nsp] exp(+eps tau) occupied, exp(-eps tau) virtual
     double *wtau = nullptr;   // [n_tau_max]
     int *tiles = nullptr;     // [n_tp][2] (P, Q), P <= Q
-    double *partial = nullptr;  // [n_tau_max][n_tp][2] per tile pair (direct, exchange)
+    int *work = nullptr;      // [n_slots / 4] tile-pair index per block (-1: idle), XCD-aware order
+    int n_slots = 0;          // partial-sum slots: 4 per block (one per wave)
+    double *partial = nullptr;  // [n_tau_max][n_slots][2] per wave slot (direct, exchange)
 
     Profiler prof;
 };
+
+// g(r) of Eq. basisSet; gpar[I] = (c1 N(z1), z1, c2 N(z2), z2).
+__device__ inline double g_value(double x, double y, double z, const double *nuc, const double *gpar, int n_nuc) {
+    double out = 0.0;
+    for (int I = 0; I < n_nuc; ++I) {
+        double dx = x - nuc[3 * I], dy = y - nuc[3 * I + 1], dz = z - nuc[3 * I + 2];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        out = out + gpar[4 * I] * exp(-gpar[4 * I + 1] * r2);
+        out = out + gpar[4 * I + 2] * exp(-gpar[4 * I + 3] * r2);
+    }
+    return out;
+}
+
+// Host: wave-slot work list of the Green's-function kernel (see green.hip).
+void build_green_work(int T, double tile_bytes, std::vector<int> &work);
 
 // error reporting (thread-local message)
 void set_error(const char *fmt, ...);
@@ -69,8 +85,9 @@ hipError_t launch_metropolis(const mcmp2_ctx *c, double *walkers, double *w, uin
                              uint64_t key1, uint64_t step, double delta, int32_t *n_acc);
 hipError_t launch_sample_tau(const mcmp2_ctx *c, uint64_t key0, uint64_t key1, uint64_t step,
                              int n_tau, double *tau);
-hipError_t launch_basis_values(const mcmp2_ctx *c, const double *walkers);
+hipError_t launch_advance(const mcmp2_ctx *c, double *walkers, double *w, uint64_t key0, uint64_t key1, uint64_t step,
+                          double delta, int32_t *n_acc, int n_tau, double *tau);
+hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau);
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c);
-hipError_t launch_tau_prep(const mcmp2_ctx *c, const double *tau, int n_tau);
 hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);

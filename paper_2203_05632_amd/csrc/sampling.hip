@@ -46,18 +46,6 @@ __device__ inline u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uin
 
 __device__ inline double to_unit(uint64_t u) { return (double)(u >> 11) * 0x1.0p-53; }
 
-// g(r) of Eq. basisSet; gpar[I] = (c1 N(z1), z1, c2 N(z2), z2).
-__device__ inline double g_value(double x, double y, double z, const double *nuc, const double *gpar, int n_nuc) {
-    double out = 0.0;
-    for (int I = 0; I < n_nuc; ++I) {
-        double dx = x - nuc[3 * I], dy = y - nuc[3 * I + 1], dz = z - nuc[3 * I + 2];
-        double r2 = dx * dx + dy * dy + dz * dz;
-        out = out + gpar[4 * I] * exp(-gpar[4 * I + 1] * r2);
-        out = out + gpar[4 * I + 2] * exp(-gpar[4 * I + 3] * r2);
-    }
-    return out;
-}
-
 __device__ inline double dist(const double *a, const double *b) {
     double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
     return sqrt(dx * dx + dy * dy + dz * dz);
@@ -76,12 +64,10 @@ __global__ void walker_weights_kernel(const double *__restrict__ walkers, int m,
     if (hinv) hinv[p] = Ng / (g1 * g2);
 }
 
-__global__ void metropolis_kernel(double *__restrict__ walkers, double *__restrict__ w, int m,
-                                  const double *__restrict__ nuc, const double *__restrict__ gpar, int n_nuc,
-                                  double Ng, uint64_t key0, uint64_t key1, uint64_t step, double delta,
-                                  int32_t *n_acc) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= m) return;
+__device__ inline void metropolis_pair(int p, double *__restrict__ walkers, double *__restrict__ w,
+                                       const double *__restrict__ nuc, const double *__restrict__ gpar, int n_nuc,
+                                       double Ng, uint64_t key0, uint64_t key1, uint64_t step, double delta,
+                                       int32_t *n_acc) {
     u64x4 a = philox4x64_10(step, (uint64_t)p, 0, 0, key0, key1);
     u64x4 b = philox4x64_10(step, (uint64_t)p, 1, 0, key0, key1);
     double u[6] = {to_unit(a.x[0]), to_unit(a.x[1]), to_unit(a.x[2]),
@@ -98,12 +84,36 @@ __global__ void metropolis_kernel(double *__restrict__ walkers, double *__restri
     }
 }
 
+__device__ inline double tau_value(int t, uint64_t key0, uint64_t key1, uint64_t step, double lambda) {
+    u64x4 a = philox4x64_10(step, (uint64_t)t, 2, 0, key0, key1);
+    return -log(1.0 - to_unit(a.x[0])) / lambda;
+}
+
+__global__ void metropolis_kernel(double *__restrict__ walkers, double *__restrict__ w, int m,
+                                  const double *__restrict__ nuc, const double *__restrict__ gpar, int n_nuc,
+                                  double Ng, uint64_t key0, uint64_t key1, uint64_t step, double delta,
+                                  int32_t *n_acc) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) metropolis_pair(p, walkers, w, nuc, gpar, n_nuc, Ng, key0, key1, step, delta, n_acc);
+}
+
 __global__ void sample_tau_kernel(uint64_t key0, uint64_t key1, uint64_t step, int n_tau, double lambda,
                                   double *tau) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tau) return;
-    u64x4 a = philox4x64_10(step, (uint64_t)t, 2, 0, key0, key1);
-    tau[t] = -log(1.0 - to_unit(a.x[0])) / lambda;
+    if (t < n_tau) tau[t] = tau_value(t, key0, key1, step, lambda);
+}
+
+// Both samplers of one MC step in a single launch: threads [0, m) move the
+// walker pairs, threads [m, m + n_tau) draw the tau samples.
+__global__ void advance_kernel(double *__restrict__ walkers, double *__restrict__ w, int m,
+                               const double *__restrict__ nuc, const double *__restrict__ gpar, int n_nuc, double Ng,
+                               uint64_t key0, uint64_t key1, uint64_t step, double delta, int32_t *n_acc, int n_tau,
+                               double lambda, double *tau) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m)
+        metropolis_pair(i, walkers, w, nuc, gpar, n_nuc, Ng, key0, key1, step, delta, n_acc);
+    else if (i < m + n_tau)
+        tau[i - m] = tau_value(i - m, key0, key1, step, lambda);
 }
 
 }  // namespace
@@ -119,6 +129,14 @@ hipError_t launch_metropolis(const mcmp2_ctx *c, double *walkers, double *w, uin
     int nb = (c->m + 63) / 64;
     metropolis_kernel<<<nb, 64, 0, c->stream>>>(walkers, w, c->m, c->nuc, c->gpar, c->n_nuc, c->Ng, key0, key1,
                                                 step, delta, n_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const mcmp2_ctx *c, double *walkers, double *w, uint64_t key0, uint64_t key1, uint64_t step,
+                          double delta, int32_t *n_acc, int n_tau, double *tau) {
+    int nb = (c->m + n_tau + 63) / 64;
+    advance_kernel<<<nb, 64, 0, c->stream>>>(walkers, w, c->m, c->nuc, c->gpar, c->n_nuc, c->Ng, key0, key1, step, delta,
+                                             n_acc, n_tau, c->lambda, tau);
     return hipGetLastError();
 }
 

@@ -139,3 +139,23 @@ def test_invalid_arguments_raise():
         _ctx(inp.with_(m=1))
     with pytest.raises(MCMP2Error):
         _ctx(inp, precision="fp32")
+
+
+def test_advance_equals_metropolis_then_sample_tau():
+    inp = make_inputs("C1")
+    ctx = _ctx(inp)
+    wk0 = dev(initial_walkers(inp))
+    w0 = torch.zeros(inp.m, dtype=torch.float64, device="cuda")
+    ctx.pair_weights(wk0, w0)
+    a_wk, a_w, b_wk, b_w = wk0.clone(), w0.clone(), wk0.clone(), w0.clone()
+    a_tau = torch.zeros(3, dtype=torch.float64, device="cuda")
+    b_tau = torch.zeros(3, dtype=torch.float64, device="cuda")
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for s in range(50):
+        ctx.advance(a_wk, a_w, (5, 6), s, 0.6, a_tau, na)
+        ctx.metropolis(b_wk, b_w, (5, 6), s, 0.6, nb)
+        ctx.sample_tau((5, 6), s, b_tau)
+    torch.cuda.synchronize()
+    assert torch.equal(a_wk, b_wk) and torch.equal(a_w, b_w) and torch.equal(a_tau, b_tau)
+    assert int(na.item()) == int(nb.item()) > 0
