@@ -73,7 +73,9 @@ typedef struct {
  *   m_pairs    : number of electron-pair walkers m (>= 2), Eq. redundant.
  *   n_tau_max  : largest n_tau a step will be given (>= 1).
  *   precision  : MCMP2_FP64 (others: MCMP2_EINVAL until implemented).
- *   want_grad  : non-zero to allow gradient outputs in mcmp2_step.
+ *   want_grad  : non-zero to allow gradient outputs in mcmp2_step; allocates
+ *                2 n_tau_max (8 m_pad)^2 complex adjoint matrices (m_pad = m
+ *                rounded up to a multiple of 8).
  *   hip_stream : hipStream_t to enqueue on (NULL = default stream).
  *   out        : receives the context.
  * lambda = 2 (eps_LUMO - eps_HOMO) (Eq. tauWeight and the rule after it) and
@@ -93,11 +95,27 @@ int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps
  *   e2_out  : device [n_tau][3]: per tau, the direct part Re(-D/2 ...), the
  *             exchange part Re(+X/2 ...) and their sum, each divided by
  *             w_p w_q w(tau) and averaged over the mC2 pairs p < q.
- *   grad_eps, grad_coeffs : must be NULL in this version (ESTATE otherwise).
+ *   grad_eps    : device [n_sp] or NULL.  dV/d eps_k of the step value
+ *                 V = (1/n_tau) sum_t e2_out[t][2], at fixed walkers, tau and
+ *                 lambda (lambda is a sampling parameter frozen at init).
+ *   grad_coeffs : device complex [2][n_L+n_S][n_sp] or NULL; dV/dRe C + i dV/dIm C.
+ *   Gradients overwrite their outputs.  Either requires want_grad at init
+ *   (ESTATE otherwise); they come from a hand-written adjoint of the same
+ *   step (Green's-function blocks recomputed, not stored between calls).
  * Errors: EINVAL (null pointers, n_tau out of range), ESTATE, EDEVICE.
  */
 int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
                double *grad_eps, double *grad_coeffs);
+
+/*
+ * mcmp2_set_coefficients -- replace the context's spinor coefficients and
+ * energies (Eq. (C), Eq. FinalMP2) with device arrays of the init layout:
+ *   coeffs : device complex [2][n_L+n_S][n_sp];  eps : device [n_sp].
+ * Copied on the context's stream (stream-ordered, no host sync).  lambda and
+ * N_g stay as frozen at init.  Either pointer may be NULL to keep that array.
+ * Errors: EINVAL (null context), EDEVICE.
+ */
+int mcmp2_set_coefficients(mcmp2_ctx *ctx, const double *coeffs, const double *eps);
 
 /*
  * mcmp2_pair_weights -- w(r1p, r2p) = g(r1p) g(r2p) / (N_g r12p) for every
@@ -167,7 +185,8 @@ enum {
     MCMP2_K_METROPOLIS = 5,     /* mcmp2_metropolis */
     MCMP2_K_SAMPLE_TAU = 6,     /* mcmp2_sample_tau */
     MCMP2_K_ADVANCE = 7,        /* mcmp2_advance */
-    MCMP2_NKERNELS = 8
+    MCMP2_K_GRAD = 8,           /* adjoint GEMMs: psi, eps and coefficient gradients */
+    MCMP2_NKERNELS = 9
 };
 int mcmp2_profile_begin(mcmp2_ctx *ctx, uint32_t mask, int32_t max_launches);
 int mcmp2_profile_end(mcmp2_ctx *ctx, double *total_ms, int64_t *launches);

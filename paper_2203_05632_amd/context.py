@@ -102,6 +102,13 @@ class Context:
                                                   name="grad_coeffs")))
         return e2_out
 
+    def set_coefficients(self, coeffs: torch.Tensor = None, eps: torch.Tensor = None) -> None:
+        """Replace the spinor coefficients / energies with device tensors (init layout)."""
+        check(self._lib.mcmp2_set_coefficients(
+            self._h,
+            None if coeffs is None else _dev(coeffs, (2, self.n_b, self.n_sp), torch.complex128, name="coeffs"),
+            None if eps is None else _dev(eps, (self.n_sp,), name="eps")))
+
     def pair_weights(self, walkers: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
         check(self._lib.mcmp2_pair_weights(self._h, _dev(walkers, (self.m, 2, 3), name="walkers"),
                                            _dev(w, (self.m,), name="w")))

@@ -38,7 +38,8 @@ void profiler_release(Profiler &p);
 void free_ctx(mcmp2_ctx *c) {
     profiler_release(c->prof);
     void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->psi,
-                    c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT};
+                    c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT,
+                    c->Hm, c->Hp, c->psibar, c->eps_part};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete c;
@@ -123,10 +124,6 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     if (precision != MCMP2_FP64) {
         set_error("precision %d not available (FP64 only)", precision);
         return MCMP2_EINVAL;
-    }
-    if (want_grad) {
-        set_error("gradients are not available in this build");
-        return MCMP2_ESTATE;
     }
     const int nb = basis->n_L + basis->n_S;
     for (int i = 0; i < nb; ++i) {
@@ -234,6 +231,16 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(dalloc(&c->work, work.size()));
     TRY(dalloc(&c->partial, (size_t)n_tau_max * c->n_slots * 2));
     TRY(dalloc(&c->XT, (size_t)nb * c->E));
+    if (want_grad) {
+        const size_t RR = (size_t)c->R * c->R;
+        TRY(dalloc(&c->Hm, 2 * (size_t)n_tau_max * RR));
+        TRY(dalloc(&c->Hp, 2 * (size_t)n_tau_max * RR));
+        TRY(dalloc(&c->psibar, 2 * (size_t)nsp * c->R));
+        TRY(dalloc(&c->eps_part, (size_t)(c->R / 32) * nsp));
+        // blocks that are never written (p = q, padding walkers) must read as zero
+        TRY(check_hip(hipMemset(c->Hm, 0, 2 * sizeof(double) * n_tau_max * RR), "hipMemset"));
+        TRY(check_hip(hipMemset(c->Hp, 0, 2 * sizeof(double) * n_tau_max * RR), "hipMemset"));
+    }
 
     auto up = [&](void *dst, const void *src, size_t bytes) {
         return check_hip(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy");
@@ -275,8 +282,9 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
         set_error("n_tau=%d outside 1..%d", n_tau, c->n_tau_max);
         return MCMP2_EINVAL;
     }
-    if (grad_eps || grad_coeffs) {
-        set_error("gradient outputs requested but not available");
+    const bool grad = grad_eps || grad_coeffs;
+    if (grad && !c->want_grad) {
+        set_error("gradient outputs requested but the context was created with want_grad = 0");
         return MCMP2_ESTATE;
     }
     int rc;
@@ -285,10 +293,29 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
         return rc;
     if ((rc = timed(c, MCMP2_K_SPINOR_GEMM, "spinor_gemm", [&] { return launch_spinor_gemm(c); })) != MCMP2_OK)
         return rc;
-    if ((rc = timed(c, MCMP2_K_GREEN_CONTRACT, "green_contract", [&] { return launch_green_contract(c, n_tau); })) !=
-        MCMP2_OK)
+    if ((rc = timed(c, MCMP2_K_GREEN_CONTRACT, "green_contract",
+                    [&] { return launch_green_contract(c, n_tau, grad); })) != MCMP2_OK)
         return rc;
-    return timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); });
+    if ((rc = timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); })) != MCMP2_OK)
+        return rc;
+    if (!grad) return MCMP2_OK;
+    return timed(c, MCMP2_K_GRAD, "grad", [&] { return launch_grad(c, tau, n_tau, grad_eps, grad_coeffs); });
+}
+
+extern "C" int mcmp2_set_coefficients(mcmp2_ctx *c, const double *coeffs, const double *eps) {
+    if (!c) {
+        set_error("null context");
+        return MCMP2_EINVAL;
+    }
+    int rc = MCMP2_OK;
+    if (coeffs)
+        rc = check_hip(hipMemcpyAsync(c->coef, coeffs, 2 * 2 * sizeof(double) * (size_t)c->nb * c->nsp,
+                                      hipMemcpyDeviceToDevice, c->stream),
+                       "hipMemcpyAsync");
+    if (rc == MCMP2_OK && eps)
+        rc = check_hip(hipMemcpyAsync(c->eps, eps, sizeof(double) * c->nsp, hipMemcpyDeviceToDevice, c->stream),
+                       "hipMemcpyAsync");
+    return rc;
 }
 
 extern "C" int mcmp2_pair_weights(mcmp2_ctx *c, const double *walkers, double *w) {

@@ -1,0 +1,226 @@
+// Gradients of the per-step value with respect to the spinor energies and
+// coefficients (reverse mode through Eq. (C) and the G+ / G- definitions of
+// Sec. III of the paper).
+//
+// The step value is V = (1/n_tau) sum_t (1/mC2) sum_{p<q} Re f / (w_p w_q w_t).
+// The Green's-function kernel, in its GRAD variant, leaves for every tau the
+// Hermitian adjoint matrices H-_t, H+_t (R x R complex): the gradient of V with
+// respect to each entry of G-_t / G+_t, folded as Gbar + Gbar^H.  Since
+// G_t = Psi S_t Psi^H with S_t = diag(exp(+eps tau)) (occupied) or
+// diag(exp(-eps tau)) (virtual),
+//   Psibar = sum_t H_t Psi S_t                                  (grad_gemm)
+//   epsbar_k = (1/2) sum_t (+-tau_t) Re(psi_k^H (H_t Psi S_t)_k) (grad_gemm + eps_reduce)
+// (the 1/2: dV/ds_k = Re(psi_k^H Gbar psi_k) = psi_k^H H psi_k / 2 for H = Gbar + Gbar^H)
+//   Cbar[s][mu][k] = sum_pt chi_mu(r_pt) Psibar[k][4 pt + c(s, mu)]   (coef_grad)
+// with the PyTorch convention dV/dRe + i dV/dIm for complex gradients.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace {
+
+constexpr int GKC = 16;  // rows y of H (and of psi) per LDS chunk
+
+// grid: (column tiles of 32 spinors: occupied tiles first, then virtual;
+//        R / 32 row tiles).  4 waves: 16x16 output sub-tiles (wx, wk).
+// Psibar[k][x] = sum_t s_t[k] sum_y H_t[x][y] psi[k][y]; the partial
+// epsbar of this row tile goes to eps_part[row tile][k].
+template <int NT>
+__global__ __launch_bounds__(256) void grad_gemm_kernel(
+    const double2 *__restrict__ Hm, const double2 *__restrict__ Hp, const double2 *__restrict__ psi,
+    const double *__restrict__ scale, const double *__restrict__ tau, int t0, int R, int no, int nsp, int n_occ_tiles,
+    bool accumulate, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
+    __shared__ double2 pa[2][NT][GKC][32];  // H_t chunk: [y][x], x fastest
+    __shared__ double2 pb[2][GKC][32];      // psi chunk: [y][k], k fastest
+    __shared__ double esum[2][32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wx = wave >> 1, wk = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    const bool occ = (int)blockIdx.x < n_occ_tiles;
+    const int k0 = occ ? 32 * blockIdx.x : no + 32 * (blockIdx.x - n_occ_tiles);
+    const int k_hi = occ ? no : nsp;
+    const double sign = occ ? 1.0 : -1.0;
+    const double2 *H = occ ? Hm : Hp;
+    const int x0 = 32 * blockIdx.y;
+    const size_t RR = (size_t)R * R;
+
+    // this lane's column k and its scalings s_t[k]
+    const int kl = k0 + 16 * wk + li;
+    const bool k_ok = kl < k_hi;
+    double s[NT];
+    for (int t = 0; t < NT; ++t) s[t] = k_ok ? scale[(size_t)(t0 + t) * nsp + kl] : 0.0;
+
+    // cooperative chunk loads: element e in {tid, tid + 256} -> (row = e / 16, y = e % 16)
+    const int e0 = tid, e1 = tid + 256;
+    double2 ra[NT][2], rb[2];
+    auto gload = [&](int y0) {
+        for (int j = 0; j < 2; ++j) {
+            const int e = j ? e1 : e0, r = e >> 4, y = y0 + (e & 15);
+            for (int t = 0; t < NT; ++t) ra[t][j] = H[(size_t)(t0 + t) * RR + (size_t)(x0 + r) * R + y];
+            const int kk = k0 + r;
+            rb[j] = kk < k_hi ? psi[(size_t)kk * R + y] : double2{0.0, 0.0};
+        }
+    };
+    auto lstore = [&](int buf) {
+        for (int j = 0; j < 2; ++j) {
+            const int e = j ? e1 : e0, r = e >> 4, y = e & 15;
+            for (int t = 0; t < NT; ++t) pa[buf][t][y][r] = ra[t][j];
+            pb[buf][y][r] = rb[j];
+        }
+    };
+
+    d4v re[NT], im[NT];
+    for (int t = 0; t < NT; ++t) re[t] = im[t] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int n_chunks = R / GKC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < n_chunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < n_chunks) gload((c + 1) * GKC);
+        for (int ks = 0; ks < GKC; ks += 4) {
+            const double2 bv = pb[buf][ks + lk][16 * wk + li];
+            for (int t = 0; t < NT; ++t) {
+                const double2 av = pa[buf][t][ks + lk][16 * wx + li];
+                const double c_ = bv.x * s[t], d_ = bv.y * s[t];
+                // (a + ib)(c + id) = (ac - bd) + i(ad + bc)
+                re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, c_, re[t], 0, 0, 0);
+                im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, d_, im[t], 0, 0, 0);
+                re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, d_, re[t], 0, 0, 0);
+                im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, c_, im[t], 0, 0, 0);
+            }
+        }
+        if (c + 1 < n_chunks) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: lane holds rows x = x0 + 16 wx + 4 v + lk, column kl
+    double e_acc = 0.0;
+    for (int v = 0; v < 4; ++v) {
+        const int x = x0 + 16 * wx + 4 * v + lk;
+        double yr = 0.0, yi = 0.0;
+        for (int t = 0; t < NT; ++t) {
+            yr += re[t][v];
+            yi += im[t][v];
+        }
+        if (k_ok) {
+            const double2 ph = psi[(size_t)kl * R + x];
+            for (int t = 0; t < NT; ++t)  // Re(conj(psi) Y_t) weighted by +-tau_t / 2
+                e_acc += 0.5 * sign * tau[t0 + t] * (ph.x * re[t][v] + ph.y * im[t][v]);
+            double2 *o = psibar + (size_t)kl * R + x;
+            if (accumulate) {
+                const double2 old = *o;
+                yr += old.x;
+                yi += old.y;
+            }
+            *o = double2{yr, yi};
+        }
+    }
+    // column sums over the 16 rows of the wave (lanes l, l^16, l^32, l^48), then the two row halves
+    e_acc += __shfl_xor(e_acc, 16, 64);
+    e_acc += __shfl_xor(e_acc, 32, 64);
+    if (lk == 0) esum[wx][16 * wk + li] = e_acc;
+    __syncthreads();
+    if (tid < 32 && k0 + tid < k_hi) {
+        double *o = eps_part + (size_t)blockIdx.y * nsp + k0 + tid;
+        const double v = esum[0][tid] + esum[1][tid];
+        *o = accumulate ? *o + v : v;
+    }
+}
+
+// epsbar[k] = sum over row tiles of eps_part, in row-tile order.
+__global__ void eps_reduce_kernel(const double *__restrict__ eps_part, int n_rowtiles, int nsp,
+                                  double *__restrict__ grad_eps) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsp) return;
+    double acc = 0.0;
+    for (int r = 0; r < n_rowtiles; ++r) acc += eps_part[(size_t)r * nsp + k];
+    grad_eps[k] = acc;
+}
+
+// Cbar[s][mu][k] = sum_pt XT[mu][pt] psibar[k][4 pt + 2 set(mu) + s].
+// grid: (mu tiles of 16: L set first, then S set; ceil(nsp / 16)); 4 waves
+// split the point range, wave 0 adds the partial tiles in a fixed order.
+__global__ __launch_bounds__(256) void coef_grad_kernel(const double *__restrict__ XT, const double2 *__restrict__ psibar,
+                                                        int E, int n_pts, int nb, int nL, int nsp, int R,
+                                                        int n_L_tiles, double2 *__restrict__ grad_coeffs) {
+    __shared__ d4v red[3][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const bool setL = (int)blockIdx.x < n_L_tiles;
+    const int mu0 = setL ? 16 * blockIdx.x : nL + 16 * (blockIdx.x - n_L_tiles);
+    const int mu_hi = setL ? nL : nb;
+    const int cbase = setL ? 0 : 2;
+    const int k0 = 16 * blockIdx.y;
+    const int mu = mu0 + li;
+    const int kB = k0 + li;  // column of this lane's B element
+    const bool mu_ok = mu < mu_hi, kB_ok = kB < nsp;
+    d4v acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int pt0 = 4 * wave; pt0 < n_pts; pt0 += 16) {
+        const int pt = pt0 + lk;
+        const bool ok = pt < n_pts;
+        const double x = (ok && mu_ok) ? XT[(size_t)mu * E + pt] : 0.0;
+        double2 ba = {0.0, 0.0}, bb = {0.0, 0.0};
+        if (ok && kB_ok) {
+            ba = psibar[(size_t)kB * R + 4 * pt + cbase];
+            bb = psibar[(size_t)kB * R + 4 * pt + cbase + 1];
+        }
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, ba.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, ba.y, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, bb.x, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, bb.y, acc[3], 0, 0, 0);
+    }
+    if (wave > 0)
+        for (int q = 0; q < 4; ++q) red[wave - 1][q][lane] = acc[q];
+    __syncthreads();
+    if (wave != 0) return;
+    for (int w = 0; w < 3; ++w)
+        for (int q = 0; q < 4; ++q) acc[q] += red[w][q][lane];
+    // result D[4 v + lk][li]: row mu = mu0 + 4 v + lk, column k = k0 + li
+    const int k = k0 + li;
+    if (k >= nsp) return;
+    for (int v = 0; v < 4; ++v) {
+        const int mr = mu0 + 4 * v + lk;
+        if (mr >= mu_hi) continue;
+        grad_coeffs[(size_t)mr * nsp + k] = double2{acc[0][v], acc[1][v]};                    // alpha
+        grad_coeffs[((size_t)nb + mr) * nsp + k] = double2{acc[2][v], acc[3][v]};             // beta
+    }
+}
+
+}  // namespace
+
+hipError_t launch_grad(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps, double *grad_coeffs) {
+    const int n_occ_tiles = (c->no + 31) / 32, n_vir_tiles = (c->nsp - c->no + 31) / 32;
+    const int n_rowtiles = c->R / 32;
+    const double2 *Hm = reinterpret_cast<const double2 *>(c->Hm), *Hp = reinterpret_cast<const double2 *>(c->Hp);
+    const double2 *psi = reinterpret_cast<const double2 *>(c->psi);
+    double2 *psibar = reinterpret_cast<double2 *>(c->psibar);
+    dim3 grid(n_occ_tiles + n_vir_tiles, n_rowtiles);
+    for (int t0 = 0; t0 < n_tau; t0 += 2) {
+        const int nt = std::min(2, n_tau - t0);
+        const bool acc = t0 > 0;
+        if (nt == 2)
+            grad_gemm_kernel<2><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
+                                                             n_occ_tiles, acc, psibar, c->eps_part);
+        else
+            grad_gemm_kernel<1><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
+                                                             n_occ_tiles, acc, psibar, c->eps_part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (grad_eps) {
+        eps_reduce_kernel<<<(c->nsp + 255) / 256, 256, 0, c->stream>>>(c->eps_part, n_rowtiles, c->nsp, grad_eps);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (grad_coeffs) {
+        const int n_L_tiles = (c->nL + 15) / 16, n_S_tiles = (c->nS + 15) / 16;
+        dim3 g2(n_L_tiles + n_S_tiles, (c->nsp + 15) / 16);
+        coef_grad_kernel<<<g2, 256, 0, c->stream>>>(c->XT, psibar, c->E, 2 * c->m, c->nb, c->nL, c->nsp, c->R,
+                                                    n_L_tiles, reinterpret_cast<double2 *>(grad_coeffs));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

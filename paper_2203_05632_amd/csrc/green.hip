@@ -43,6 +43,9 @@ __device__ inline cplx cmulc(cplx a, cplx b) {  // conj(a) * b
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 __device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline cplx conjc(cplx a) { return {a.re, -a.im}; }
+__device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
 __device__ inline cplx shfl_xor_c(cplx a, int mask) {
     return {__shfl_xor(a.re, mask, 64), __shfl_xor(a.im, mask, 64)};
 }
@@ -199,11 +202,15 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
 }
 
 // grid: n_slots / 4 blocks; tau samples t0 .. t0 + NT - 1.
-template <int NT>
+// GRAD: also write, per walker pair, the 8x8 blocks of the Hermitian adjoint
+// matrices H- and H+ (gradient of the step value with respect to the entries
+// of G- and G+, folded as Gbar + Gbar^H) into Hm / Hp [n_tau][R][R] complex.
+template <int NT, bool GRAD>
 __global__ __launch_bounds__(256) void green_contract_kernel(
     const double *__restrict__ psi_, const double *__restrict__ scale, const double *__restrict__ wtau,
     const double *__restrict__ hinv, const int *__restrict__ tiles, const int *__restrict__ work, int n_slots, int R,
-    int no, int nsp, int m, int t0, double *__restrict__ partial) {
+    int no, int nsp, int m, int t0, double *__restrict__ partial, double2 *__restrict__ Hm, double2 *__restrict__ Hp,
+    double cgrad) {
     // 2 buffers x (A, B) x KC x 32 complex = 32 KB; reused for the G tiles of the epilogue
     __shared__ double2 panel[2][2][KC][32];
     __shared__ double spanel[2][4 * KC];  // tau scalings of the buffered chunks
@@ -255,7 +262,6 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
             m1 = cadd(m1, cmulc(GB(Gm, 0, 0, k, a), GB(Gp, 0, 1, k, b)));  // [G-(1,3)^H G+(1,4)]_{ab}
             m2 = cadd(m2, cmulc(GB(Gm, 1, 1, k, b), GB(Gp, 1, 0, k, a)));  // [G-(2,4)^H G+(2,3)]_{ba}
         }
-#undef GB
         cplx xt = cmul(m1, m2);
         for (int mask = 8; mask >= 1; mask >>= 1) {
             t1 = cadd(t1, shfl_xor_c(t1, mask));
@@ -268,7 +274,46 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
             const cplx D = cmul(t1, t2);
             dir = -0.5 * D.re * W;
             exc = 0.5 * xt.re * W;
+            if constexpr (GRAD) {
+                // Adjoint of c Re(t1 t2 - X), c = cgrad W, with the stored blocks
+                // A13 = G-(1,3), A24 = G-(2,4), P13 = G+(1,3), P14, P23, P24
+                // (G-(3,1) = A13^H, G-(4,2) = A24^H):
+                //   H-(1,3) = c (t2 P13 - P14 A24^H P23)   H-(2,4) = c (t1 P24 - P23 A13^H P14)
+                //   H+(1,3) = c conj(t2) A13              H+(2,4) = c conj(t1) A24
+                //   H+(1,4) = -c A13 P23^H A24            H+(2,3) = -c A24 P14^H A13
+                // Lane (a, b) forms element [a][b] of each block.
+                const double cw = cgrad * W;
+                cplx s13 = {0.0, 0.0}, s24 = {0.0, 0.0}, s14 = {0.0, 0.0}, s23 = {0.0, 0.0};
+                for (int k = 0; k < 4; ++k)
+                    for (int l = 0; l < 4; ++l) {
+                        s13 = cadd(s13, cmul(cmul(GB(Gp, 0, 1, a, k), conjc(GB(Gm, 1, 1, l, k))), GB(Gp, 1, 0, l, b)));
+                        s24 = cadd(s24, cmul(cmul(GB(Gp, 1, 0, a, k), conjc(GB(Gm, 0, 0, l, k))), GB(Gp, 0, 1, l, b)));
+                        s14 = cadd(s14, cmul(cmul(GB(Gm, 0, 0, a, k), conjc(GB(Gp, 1, 0, l, k))), GB(Gm, 1, 1, l, b)));
+                        s23 = cadd(s23, cmul(cmul(GB(Gm, 1, 1, a, k), conjc(GB(Gp, 0, 1, l, k))), GB(Gm, 0, 0, l, b)));
+                    }
+                const cplx p13 = GB(Gp, 0, 0, a, b), p24 = GB(Gp, 1, 1, a, b);
+                const cplx a13 = GB(Gm, 0, 0, a, b), a24 = GB(Gm, 1, 1, a, b);
+                const cplx hm13 = cscale(csub(cmul(t2, p13), s13), cw);
+                const cplx hm24 = cscale(csub(cmul(t1, p24), s24), cw);
+                const cplx hp13 = cscale(cmul(conjc(t2), a13), cw);
+                const cplx hp24 = cscale(cmul(conjc(t1), a24), cw);
+                const cplx hp14 = cscale(s14, -cw);
+                const cplx hp23 = cscale(s23, -cw);
+                const size_t RR = (size_t)R * R, off = (size_t)(t0 + t) * RR;
+                const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
+                auto put = [&](double2 *H, size_t r, size_t cc, cplx v) {
+                    H[off + r * R + cc] = double2{v.re, v.im};
+                    H[off + cc * R + r] = double2{v.re, -v.im};  // Hermitian partner block (q, p)
+                };
+                put(Hm, r1, c3, hm13);
+                put(Hm, r2, c4, hm24);
+                put(Hp, r1, c3, hp13);
+                put(Hp, r2, c4, hp24);
+                put(Hp, r1, c4, hp14);
+                put(Hp, r2, c3, hp23);
+            }
         }
+#undef GB
         // pairs of this wave summed in a fixed order (lanes 0, 16, 32, 48)
         const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
                      d3 = __shfl(dir, 48, 64);
@@ -330,14 +375,24 @@ void build_green_work(int T, double tile_bytes, std::vector<int> &work) {
     }
 }
 
-hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau) {
+hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
+    // gradient of the step value (mean over tau of the pair average): c = -1/2 / (mC2 n_tau)
+    const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
+    double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
     const int nblocks = c->n_slots / 4;  // one work-list entry per block, four partial slots
     for (int t0 = 0; t0 < n_tau; t0 += 4) {
         const int nt = std::min(4, n_tau - t0);
-#define LAUNCH(NTV)                                                                                                  \
-    green_contract_kernel<NTV><<<nblocks, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv, c->tiles,        \
-                                                               c->work, c->n_slots, c->R, c->no, c->nsp, c->m, t0, \
-                                                               c->partial)
+#define LAUNCH(NTV)                                                                                              \
+    if (grad)                                                                                                    \
+        green_contract_kernel<NTV, true><<<nblocks, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,     \
+                                                                         c->tiles, c->work, c->n_slots, c->R,    \
+                                                                         c->no, c->nsp, c->m, t0, c->partial, Hm, \
+                                                                         Hp, cgrad);                             \
+    else                                                                                                         \
+        green_contract_kernel<NTV, false><<<nblocks, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,    \
+                                                                          c->tiles, c->work, c->n_slots, c->R,   \
+                                                                          c->no, c->nsp, c->m, t0, c->partial,   \
+                                                                          nullptr, nullptr, 0.0)
         switch (nt) {
             case 1: LAUNCH(1); break;
             case 2: LAUNCH(2); break;

@@ -56,6 +56,11 @@ struct mcmp2_ctx {
     int *work = nullptr;      // [n_slots / 4] tile-pair index per block (-1: idle), XCD-aware order
     int n_slots = 0;          // partial-sum slots: 4 per block (one per wave)
     double *partial = nullptr;  // [n_tau_max][n_slots][2] per wave slot (direct, exchange)
+    // gradient work space (allocated when want_grad)
+    double *Hm = nullptr;       // [n_tau_max][R][R] complex adjoint of G-
+    double *Hp = nullptr;       // [n_tau_max][R][R] complex adjoint of G+
+    double *psibar = nullptr;   // [nsp][R] complex gradient of psi
+    double *eps_part = nullptr; // [R / 32][nsp] per row tile
 
     Profiler prof;
 };
@@ -89,5 +94,6 @@ hipError_t launch_advance(const mcmp2_ctx *c, double *walkers, double *w, uint64
                           double delta, int32_t *n_acc, int n_tau, double *tau);
 hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau);
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c);
-hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau);
+hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad);
+hipError_t launch_grad(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps, double *grad_coeffs);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);
