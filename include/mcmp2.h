@@ -72,7 +72,12 @@ typedef struct {
  *   eps        : host, [n_occ+n_vir] spinor energies, occupied first.
  *   m_pairs    : number of electron-pair walkers m (>= 2), Eq. redundant.
  *   n_tau_max  : largest n_tau a step will be given (>= 1).
- *   precision  : MCMP2_FP64 (others: MCMP2_EINVAL until implemented).
+ *   precision  : MCMP2_FP64: every GEMM in FP64.  MCMP2_FP32 / _BF16 / _FP16:
+ *                the spinor GEMM on FP32 MFMA and the Green's-function GEMMs on
+ *                FP32 / BF16 / FP16 MFMA operands, all with FP32 accumulation;
+ *                exp(+-eps tau) scalings (applied as square roots to both
+ *                operands), weights, contractions, adjoint GEMMs and all sums
+ *                stay in FP64.
  *   want_grad  : non-zero to allow gradient outputs in mcmp2_step; allocates
  *                2 n_tau_max (8 m_pad)^2 complex adjoint matrices (m_pad = m
  *                rounded up to a multiple of 8).
@@ -160,6 +165,17 @@ int mcmp2_advance(mcmp2_ctx *ctx, double *walkers, double *w, uint64_t key0, uin
                   double delta, int32_t *n_accepted, int32_t n_tau, double *tau);
 
 /*
+ * mcmp2_accumulate -- compensated (Neumaier) accumulation across MC steps:
+ * for i < n, (sum[i], comp[i]) += src[i], so that sum[i] + comp[i] carries the
+ * running total of every src added since the pair was zeroed (per-step E2
+ * parts, eps gradients or, as 2 n doubles, complex coefficient gradients).
+ *   src, sum, comp : device [n] doubles; n >= 0.  The caller zeroes sum and
+ *   comp to start; calls are ordered on the context's stream.
+ * Errors: EINVAL (null pointers with n > 0, n < 0), EDEVICE.
+ */
+int mcmp2_accumulate(mcmp2_ctx *ctx, const double *src, double *sum, double *comp, int64_t n);
+
+/*
  * mcmp2_constants -- host copies of the frozen sampling constants.
  *   lambda, n_g : host outputs (either may be NULL).
  */
@@ -186,7 +202,8 @@ enum {
     MCMP2_K_SAMPLE_TAU = 6,     /* mcmp2_sample_tau */
     MCMP2_K_ADVANCE = 7,        /* mcmp2_advance */
     MCMP2_K_GRAD = 8,           /* adjoint GEMMs: psi, eps and coefficient gradients */
-    MCMP2_NKERNELS = 9
+    MCMP2_K_ACCUMULATE = 9,     /* mcmp2_accumulate */
+    MCMP2_NKERNELS = 10
 };
 int mcmp2_profile_begin(mcmp2_ctx *ctx, uint32_t mask, int32_t max_launches);
 int mcmp2_profile_end(mcmp2_ctx *ctx, double *total_ms, int64_t *launches);

@@ -16,10 +16,10 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 
 # Every symbol declared in include/mcmp2.h.
 EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_set_coefficients", "mcmp2_pair_weights", "mcmp2_metropolis", "mcmp2_sample_tau",
-           "mcmp2_advance", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_destroy",
+           "mcmp2_advance", "mcmp2_accumulate", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_destroy",
            "mcmp2_last_error"]
 KERNELS = ["walker_weights", "step_prep", "spinor_gemm", "green_contract", "reduce", "metropolis", "sample_tau",
-           "advance", "grad"]
+           "advance", "grad", "accumulate"]
 
 
 class Basis(ctypes.Structure):
@@ -68,6 +68,8 @@ def load() -> ctypes.CDLL:
     lib.mcmp2_sample_tau.restype = ctypes.c_int
     lib.mcmp2_advance.argtypes = [vp, vp, vp, u64, u64, u64, dbl, vp, i32, vp]
     lib.mcmp2_advance.restype = ctypes.c_int
+    lib.mcmp2_accumulate.argtypes = [vp, vp, vp, vp, ctypes.c_int64]
+    lib.mcmp2_accumulate.restype = ctypes.c_int
     lib.mcmp2_constants.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.mcmp2_constants.restype = ctypes.c_int
     lib.mcmp2_profile_begin.argtypes = [vp, ctypes.c_uint32, i32]

@@ -138,6 +138,17 @@ class Context:
                                          _dev(tau, (n,), name="tau")))
         return tau
 
+    def accumulate(self, src: torch.Tensor, acc_sum: torch.Tensor, acc_comp: torch.Tensor) -> None:
+        """Compensated accumulation (acc_sum, acc_comp) += src (float64 or complex128 device tensors)."""
+        if not (src.shape == acc_sum.shape == acc_comp.shape and src.dtype == acc_sum.dtype == acc_comp.dtype):
+            raise ValueError("src, acc_sum and acc_comp must share shape and dtype")
+        if src.dtype not in (torch.float64, torch.complex128):
+            raise TypeError("accumulate takes float64 or complex128 tensors")
+        n = src.numel() * (2 if src.is_complex() else 1)
+        check(self._lib.mcmp2_accumulate(self._h, _dev(src, dtype=src.dtype, name="src"),
+                                         _dev(acc_sum, dtype=src.dtype, name="acc_sum"),
+                                         _dev(acc_comp, dtype=src.dtype, name="acc_comp"), n))
+
     def profile_begin(self, kernels, max_launches: int) -> None:
         """Time every launch of the named kernels with HIP events on the context's stream."""
         mask = 0

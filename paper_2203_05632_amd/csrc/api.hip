@@ -39,7 +39,7 @@ void free_ctx(mcmp2_ctx *c) {
     profiler_release(c->prof);
     void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->psi,
                     c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT,
-                    c->Hm, c->Hp, c->psibar, c->eps_part};
+                    c->Hm, c->Hp, c->psibar, c->eps_part, c->U};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete c;
@@ -121,8 +121,8 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
                   basis->n_L, basis->n_S, n_occ, n_vir, m_pairs, n_tau_max);
         return MCMP2_EINVAL;
     }
-    if (precision != MCMP2_FP64) {
-        set_error("precision %d not available (FP64 only)", precision);
+    if (precision < MCMP2_FP64 || precision > MCMP2_FP16) {
+        set_error("precision %d is not one of MCMP2_FP64, _FP32, _BF16, _FP16", precision);
         return MCMP2_EINVAL;
     }
     const int nb = basis->n_L + basis->n_S;
@@ -182,6 +182,10 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     c->precision = precision;
     c->want_grad = want_grad;
     c->lambda = lambda;
+    // low-precision operand layout: K extents (reals) padded to multiples of 32
+    c->Ko = (2 * n_occ + 31) / 32 * 32;
+    c->Ktot = c->Ko + (2 * n_vir + 31) / 32 * 32;
+    const size_t op_bytes = precision == MCMP2_FP32 ? 4 : 2;
 
     // N_g = sum over all pairs of weight-function Gaussians (Sec. III).
     std::vector<double> gpar(4 * (size_t)c->n_nuc);
@@ -220,12 +224,20 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(dalloc(&c->coef, 2 * 2 * (size_t)nb * nsp));
     TRY(dalloc(&c->eps, (size_t)nsp));
     TRY(dalloc(&c->hinv, (size_t)c->m_pad));
-    TRY(dalloc(&c->psi, 2 * (size_t)nsp * c->R));
+    TRY(dalloc(&c->psi, 2 * (size_t)nsp * c->R));  // double2 (FP64) or float2 (low precision)
+    if (precision != MCMP2_FP64) {
+        unsigned char *u = nullptr;
+        const size_t ub = op_bytes * (size_t)n_tau_max * c->R * c->Ktot;
+        TRY(dalloc(&u, ub));
+        c->U = u;
+        TRY(check_hip(hipMemset(c->U, 0, ub), "hipMemset"));  // K padding stays zero
+    }
     TRY(dalloc(&c->scale, (size_t)n_tau_max * nsp));
     TRY(dalloc(&c->wtau, (size_t)n_tau_max));
     std::vector<int> work;
-    // one block tile's psi rows: 8 kTileWalkers rows x n_sp complex FP64
-    build_green_work(c->T, 8.0 * kTileWalkers * 16.0 * nsp, work);
+    // bytes of one block tile's operand rows: 8 kTileWalkers rows of all spinors
+    const double row_bytes = precision == MCMP2_FP64 ? 16.0 * nsp : (double)op_bytes * c->Ktot;
+    build_green_work(c->T, 8.0 * kTileWalkers * row_bytes, work);
     c->n_slots = 4 * (int)work.size();
     TRY(dalloc(&c->tiles, 2 * (size_t)c->n_tp));
     TRY(dalloc(&c->work, work.size()));
@@ -293,8 +305,9 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
         return rc;
     if ((rc = timed(c, MCMP2_K_SPINOR_GEMM, "spinor_gemm", [&] { return launch_spinor_gemm(c); })) != MCMP2_OK)
         return rc;
-    if ((rc = timed(c, MCMP2_K_GREEN_CONTRACT, "green_contract",
-                    [&] { return launch_green_contract(c, n_tau, grad); })) != MCMP2_OK)
+    if ((rc = timed(c, MCMP2_K_GREEN_CONTRACT, "green_contract", [&] {
+             return c->precision == MCMP2_FP64 ? launch_green_contract(c, n_tau, grad) : launch_green_lp(c, n_tau, grad);
+         })) != MCMP2_OK)
         return rc;
     if ((rc = timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); })) != MCMP2_OK)
         return rc;
@@ -369,6 +382,14 @@ extern "C" int mcmp2_sample_tau(mcmp2_ctx *c, uint64_t key0, uint64_t key1, uint
         return MCMP2_EINVAL;
     }
     return timed(c, MCMP2_K_SAMPLE_TAU, "sample_tau", [&] { return launch_sample_tau(c, key0, key1, step, n_tau, tau); });
+}
+
+extern "C" int mcmp2_accumulate(mcmp2_ctx *c, const double *src, double *sum, double *comp, int64_t n) {
+    if (!c || n < 0 || (n > 0 && (!src || !sum || !comp))) {
+        set_error("null argument or negative n");
+        return MCMP2_EINVAL;
+    }
+    return timed(c, MCMP2_K_ACCUMULATE, "accumulate", [&] { return launch_accumulate(c, src, sum, comp, n); });
 }
 
 extern "C" int mcmp2_constants(const mcmp2_ctx *c, double *lambda, double *n_g) {

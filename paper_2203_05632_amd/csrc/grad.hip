@@ -25,9 +25,13 @@ constexpr int GKC = 16;  // rows y of H (and of psi) per LDS chunk
 //        R / 32 row tiles).  4 waves: 16x16 output sub-tiles (wx, wk).
 // Psibar[k][x] = sum_t s_t[k] sum_y H_t[x][y] psi[k][y]; the partial
 // epsbar of this row tile goes to eps_part[row tile][k].
-template <int NT>
+__device__ inline double2 to_d2(const double2 &v) { return v; }
+__device__ inline double2 to_d2(const float2 &v) { return double2{(double)v.x, (double)v.y}; }
+
+// P: element type of psi (double2 in FP64 mode, float2 in the low-precision modes)
+template <int NT, typename P>
 __global__ __launch_bounds__(256) void grad_gemm_kernel(
-    const double2 *__restrict__ Hm, const double2 *__restrict__ Hp, const double2 *__restrict__ psi,
+    const double2 *__restrict__ Hm, const double2 *__restrict__ Hp, const P *__restrict__ psi,
     const double *__restrict__ scale, const double *__restrict__ tau, int t0, int R, int no, int nsp, int n_occ_tiles,
     bool accumulate, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
     __shared__ double2 pa[2][NT][GKC][32];  // H_t chunk: [y][x], x fastest
@@ -58,7 +62,7 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
             const int e = j ? e1 : e0, r = e >> 4, y = y0 + (e & 15);
             for (int t = 0; t < NT; ++t) ra[t][j] = H[(size_t)(t0 + t) * RR + (size_t)(x0 + r) * R + y];
             const int kk = k0 + r;
-            rb[j] = kk < k_hi ? psi[(size_t)kk * R + y] : double2{0.0, 0.0};
+            rb[j] = kk < k_hi ? to_d2(psi[(size_t)kk * R + y]) : double2{0.0, 0.0};
         }
     };
     auto lstore = [&](int buf) {
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
             yi += im[t][v];
         }
         if (k_ok) {
-            const double2 ph = psi[(size_t)kl * R + x];
+            const double2 ph = to_d2(psi[(size_t)kl * R + x]);
             for (int t = 0; t < NT; ++t)  // Re(conj(psi) Y_t) weighted by +-tau_t / 2
                 e_acc += 0.5 * sign * tau[t0 + t] * (ph.x * re[t][v] + ph.y * im[t][v]);
             double2 *o = psibar + (size_t)kl * R + x;
@@ -188,25 +192,37 @@ __global__ __launch_bounds__(256) void coef_grad_kernel(const double *__restrict
     }
 }
 
+template <typename P>
+hipError_t launch_grad_gemm(const mcmp2_ctx *c, const double *tau, int n_tau, int n_occ_tiles, int n_vir_tiles) {
+    const double2 *Hm = reinterpret_cast<const double2 *>(c->Hm), *Hp = reinterpret_cast<const double2 *>(c->Hp);
+    const P *psi = reinterpret_cast<const P *>(c->psi);
+    double2 *psibar = reinterpret_cast<double2 *>(c->psibar);
+    dim3 grid(n_occ_tiles + n_vir_tiles, c->R / 32);
+    for (int t0 = 0; t0 < n_tau; t0 += 2) {
+        const int nt = std::min(2, n_tau - t0);
+        const bool acc = t0 > 0;
+        if (nt == 2)
+            grad_gemm_kernel<2, P><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
+                                                                n_occ_tiles, acc, psibar, c->eps_part);
+        else
+            grad_gemm_kernel<1, P><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
+                                                                n_occ_tiles, acc, psibar, c->eps_part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 hipError_t launch_grad(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps, double *grad_coeffs) {
     const int n_occ_tiles = (c->no + 31) / 32, n_vir_tiles = (c->nsp - c->no + 31) / 32;
     const int n_rowtiles = c->R / 32;
-    const double2 *Hm = reinterpret_cast<const double2 *>(c->Hm), *Hp = reinterpret_cast<const double2 *>(c->Hp);
-    const double2 *psi = reinterpret_cast<const double2 *>(c->psi);
     double2 *psibar = reinterpret_cast<double2 *>(c->psibar);
-    dim3 grid(n_occ_tiles + n_vir_tiles, n_rowtiles);
-    for (int t0 = 0; t0 < n_tau; t0 += 2) {
-        const int nt = std::min(2, n_tau - t0);
-        const bool acc = t0 > 0;
-        if (nt == 2)
-            grad_gemm_kernel<2><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
-                                                             n_occ_tiles, acc, psibar, c->eps_part);
-        else
-            grad_gemm_kernel<1><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
-                                                             n_occ_tiles, acc, psibar, c->eps_part);
-        hipError_t e = hipGetLastError();
+    {
+        hipError_t e = c->precision == MCMP2_FP64
+                           ? launch_grad_gemm<double2>(c, tau, n_tau, n_occ_tiles, n_vir_tiles)
+                           : launch_grad_gemm<float2>(c, tau, n_tau, n_occ_tiles, n_vir_tiles);
         if (e != hipSuccess) return e;
     }
     if (grad_eps) {

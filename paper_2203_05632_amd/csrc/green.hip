@@ -31,24 +31,9 @@
 // slices fit that XCD's L2 (build_green_work).
 #include <algorithm>
 
-#include "internal.hpp"
+#include "contract.hpp"
 
 namespace {
-
-struct cplx {
-    double re, im;
-};
-__device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ inline cplx cmulc(cplx a, cplx b) {  // conj(a) * b
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
-}
-__device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
-__device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
-__device__ inline cplx conjc(cplx a) { return {a.re, -a.im}; }
-__device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
-__device__ inline cplx shfl_xor_c(cplx a, int mask) {
-    return {__shfl_xor(a.re, mask, 64), __shfl_xor(a.im, mask, 64)};
-}
 
 // Neumaier (improved Kahan) summation: s + c carries the running total.
 __device__ inline void neumaier_add(double &s, double &c, double x) {
@@ -241,10 +226,6 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
     // epilogue: per tau, stage the wave's G- and G+ sub-tiles in LDS and contract
     cplx *Gm = reinterpret_cast<cplx *>(&panel[0][0][0][0]) + wave * 512;
     cplx *Gp = Gm + 256;
-    const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
-    const int a = (lane & 15) >> 2, b = lane & 3;
-    const int p = 4 * PT + 2 * wp + pp, q = 4 * QT + 2 * wq + qq;
-    const bool pair_ok = p < q && q < m;
     const int slot = 4 * blockIdx.x + wave;
     for (int t = 0; t < NT; ++t) {
         for (int v = 0; v < 4; ++v) {
@@ -253,77 +234,10 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
             Gp[i * 16 + li] = {gp_re[t][v], gp_im[t][v]};
         }
         __syncthreads();
-        // block (e, f) of the pair: rows 8 pp + 4 e + i, cols 8 qq + 4 f + j
-#define GB(G, e, f, i, j) G[(8 * pp + 4 * (e) + (i)) * 16 + 8 * qq + 4 * (f) + (j)]
-        cplx t1 = cmulc(GB(Gm, 0, 0, a, b), GB(Gp, 0, 0, a, b));
-        cplx t2 = cmulc(GB(Gm, 1, 1, a, b), GB(Gp, 1, 1, a, b));
-        cplx m1 = {0.0, 0.0}, m2 = {0.0, 0.0};
-        for (int k = 0; k < 4; ++k) {
-            m1 = cadd(m1, cmulc(GB(Gm, 0, 0, k, a), GB(Gp, 0, 1, k, b)));  // [G-(1,3)^H G+(1,4)]_{ab}
-            m2 = cadd(m2, cmulc(GB(Gm, 1, 1, k, b), GB(Gp, 1, 0, k, a)));  // [G-(2,4)^H G+(2,3)]_{ba}
-        }
-        cplx xt = cmul(m1, m2);
-        for (int mask = 8; mask >= 1; mask >>= 1) {
-            t1 = cadd(t1, shfl_xor_c(t1, mask));
-            t2 = cadd(t2, shfl_xor_c(t2, mask));
-            xt = cadd(xt, shfl_xor_c(xt, mask));
-        }
-        double dir = 0.0, exc = 0.0;
-        if (pair_ok) {
-            const double W = hinv[p] * hinv[q] / wtau[t0 + t];
-            const cplx D = cmul(t1, t2);
-            dir = -0.5 * D.re * W;
-            exc = 0.5 * xt.re * W;
-            if constexpr (GRAD) {
-                // Adjoint of c Re(t1 t2 - X), c = cgrad W, with the stored blocks
-                // A13 = G-(1,3), A24 = G-(2,4), P13 = G+(1,3), P14, P23, P24
-                // (G-(3,1) = A13^H, G-(4,2) = A24^H):
-                //   H-(1,3) = c (t2 P13 - P14 A24^H P23)   H-(2,4) = c (t1 P24 - P23 A13^H P14)
-                //   H+(1,3) = c conj(t2) A13              H+(2,4) = c conj(t1) A24
-                //   H+(1,4) = -c A13 P23^H A24            H+(2,3) = -c A24 P14^H A13
-                // Lane (a, b) forms element [a][b] of each block.
-                const double cw = cgrad * W;
-                cplx s13 = {0.0, 0.0}, s24 = {0.0, 0.0}, s14 = {0.0, 0.0}, s23 = {0.0, 0.0};
-                for (int k = 0; k < 4; ++k)
-                    for (int l = 0; l < 4; ++l) {
-                        s13 = cadd(s13, cmul(cmul(GB(Gp, 0, 1, a, k), conjc(GB(Gm, 1, 1, l, k))), GB(Gp, 1, 0, l, b)));
-                        s24 = cadd(s24, cmul(cmul(GB(Gp, 1, 0, a, k), conjc(GB(Gm, 0, 0, l, k))), GB(Gp, 0, 1, l, b)));
-                        s14 = cadd(s14, cmul(cmul(GB(Gm, 0, 0, a, k), conjc(GB(Gp, 1, 0, l, k))), GB(Gm, 1, 1, l, b)));
-                        s23 = cadd(s23, cmul(cmul(GB(Gm, 1, 1, a, k), conjc(GB(Gp, 0, 1, l, k))), GB(Gm, 0, 0, l, b)));
-                    }
-                const cplx p13 = GB(Gp, 0, 0, a, b), p24 = GB(Gp, 1, 1, a, b);
-                const cplx a13 = GB(Gm, 0, 0, a, b), a24 = GB(Gm, 1, 1, a, b);
-                const cplx hm13 = cscale(csub(cmul(t2, p13), s13), cw);
-                const cplx hm24 = cscale(csub(cmul(t1, p24), s24), cw);
-                const cplx hp13 = cscale(cmul(conjc(t2), a13), cw);
-                const cplx hp24 = cscale(cmul(conjc(t1), a24), cw);
-                const cplx hp14 = cscale(s14, -cw);
-                const cplx hp23 = cscale(s23, -cw);
-                const size_t RR = (size_t)R * R, off = (size_t)(t0 + t) * RR;
-                const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
-                auto put = [&](double2 *H, size_t r, size_t cc, cplx v) {
-                    H[off + r * R + cc] = double2{v.re, v.im};
-                    H[off + cc * R + r] = double2{v.re, -v.im};  // Hermitian partner block (q, p)
-                };
-                put(Hm, r1, c3, hm13);
-                put(Hm, r2, c4, hm24);
-                put(Hp, r1, c3, hp13);
-                put(Hp, r2, c4, hp24);
-                put(Hp, r1, c4, hp14);
-                put(Hp, r2, c3, hp23);
-            }
-        }
-#undef GB
-        // pairs of this wave summed in a fixed order (lanes 0, 16, 32, 48)
-        const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
-                     d3 = __shfl(dir, 48, 64);
-        const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
-                     x3 = __shfl(exc, 48, 64);
-        if (lane == 0) {
-            double *out = partial + ((size_t)(t0 + t) * n_slots + slot) * 2;
-            out[0] = ((d0 + d1) + d2) + d3;
-            out[1] = ((x0 + x1) + x2) + x3;
-        }
+        contract_pairs<GRAD>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
+                             partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
+                             GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
+                             GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
         __syncthreads();  // the sub-tiles are rewritten for the next tau
     }
 }

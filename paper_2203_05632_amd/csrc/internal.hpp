@@ -49,7 +49,9 @@ struct mcmp2_ctx {
     double *eps = nullptr;    // [nsp]
     double *XT = nullptr;     // [nb][E] basis values, point fastest (padding points stay zero)
     double *hinv = nullptr;   // [m_pad] N_g / (g(r1p) g(r2p))
-    double *psi = nullptr;    // [nsp][R] complex, row fastest
+    double *psi = nullptr;    // [nsp][R] complex, row fastest (double2; float2 for low-precision modes)
+    void *U = nullptr;        // low-precision modes: [n_tau_max][R][Ktot] scaled operands (see green_lp.hip)
+    int Ko = 0, Ktot = 0;     // K extents of the occupied segment and of all spinors (reals, multiples of 32)
     double *scale = nullptr;  // [n_tau_max][nsp] exp(+eps tau) occupied, exp(-eps tau) virtual
     double *wtau = nullptr;   // [n_tau_max]
     int *tiles = nullptr;     // [n_tp][2] (P, Q), P <= Q
@@ -95,5 +97,7 @@ hipError_t launch_advance(const mcmp2_ctx *c, double *walkers, double *w, uint64
 hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau);
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c);
 hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad);
+hipError_t launch_green_lp(const mcmp2_ctx *c, int n_tau, bool grad);
+hipError_t launch_accumulate(const mcmp2_ctx *c, const double *src, double *sum, double *comp, int64_t n);
 hipError_t launch_grad(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps, double *grad_coeffs);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);

@@ -11,6 +11,8 @@
 // evaluation of the same expression.
 #pragma clang fp contract(off)
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace {
@@ -116,7 +118,24 @@ __global__ void advance_kernel(double *__restrict__ walkers, double *__restrict_
         tau[i - m] = tau_value(i - m, key0, key1, step, lambda);
 }
 
+// Neumaier step: (s, c) += x with the rounding error of s + x kept in c.
+__global__ void accumulate_kernel(const double *__restrict__ src, double *__restrict__ sum, double *__restrict__ comp,
+                                  int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double s = sum[i], x = src[i], t = s + x;
+        comp[i] += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+        sum[i] = t;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_accumulate(const mcmp2_ctx *c, const double *src, double *sum, double *comp, int64_t n) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    accumulate_kernel<<<(int)blocks, 256, 0, c->stream>>>(src, sum, comp, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_walker_weights(const mcmp2_ctx *c, const double *walkers, double *w, double *hinv) {
     int nb = (c->m + 63) / 64;

@@ -78,10 +78,17 @@ __global__ __launch_bounds__(128) void step_prep_kernel(
 // f64): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the result
 // D[4 v + l / 16][l % 16] sits in element v of the lane's accumulator
 // (checked on gfx950).
+//
+// T = double: FP64 MFMA, psi double2.  T = float: v_mfma_f32_16x16x4f32 on
+// operands rounded from FP64, FP32 accumulation, psi float2 (the operand
+// source of the low-precision Green's-function kernels); its result element v
+// sits at D[4 (l / 16) + v][l % 16].
+template <typename T>
 __global__ __launch_bounds__(256) void spinor_gemm_kernel(const double *__restrict__ XT,
                                                           const double *__restrict__ coef, int E, int nb, int nL,
-                                                          int nsp, int R, double *__restrict__ psi) {
-    __shared__ d4v red[3][4][64];
+                                                          int nsp, int R, void *__restrict__ psi_out) {
+    typedef T acc_t __attribute__((ext_vector_type(4)));
+    __shared__ acc_t red[3][4][64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int set = blockIdx.z;
@@ -97,8 +104,14 @@ __global__ __launch_bounds__(256) void spinor_gemm_kernel(const double *__restri
     const size_t spin_stride = (size_t)nb * nsp;  // complex elements
     const double *Xp = XT + pt0 + li;
 
-    d4v acc[4];
-    for (int q = 0; q < 4; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
+    acc_t acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = acc_t{0, 0, 0, 0};
+    auto mfma = [](double a, double b, acc_t c) -> acc_t {
+        if constexpr (__is_same(T, double))
+            return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        else
+            return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+    };
 
     // K-steps of this wave: mu groups mu_lo + 4 wave + 16 j.  They are
     // fetched in batches of BK into registers; batch b + 1 is requested before
@@ -121,10 +134,10 @@ __global__ __launch_bounds__(256) void spinor_gemm_kernel(const double *__restri
             const bool ok = mu_first + 16 * j + lk < mu_hi;
             const double xv = ok ? st.x[j] : 0.0;
             const bool okc = ok && k_ok;
-            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(okc ? st.ca[j].x : 0.0, xv, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(okc ? st.ca[j].y : 0.0, xv, acc[1], 0, 0, 0);
-            acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(okc ? st.cb[j].x : 0.0, xv, acc[2], 0, 0, 0);
-            acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(okc ? st.cb[j].y : 0.0, xv, acc[3], 0, 0, 0);
+            acc[0] = mfma(okc ? st.ca[j].x : 0.0, xv, acc[0]);
+            acc[1] = mfma(okc ? st.ca[j].y : 0.0, xv, acc[1]);
+            acc[2] = mfma(okc ? st.cb[j].x : 0.0, xv, acc[2]);
+            acc[3] = mfma(okc ? st.cb[j].y : 0.0, xv, acc[3]);
         }
     };
     const int mu_w = mu_lo + 4 * wave;
@@ -155,12 +168,13 @@ __global__ __launch_bounds__(256) void spinor_gemm_kernel(const double *__restri
     for (int w = 0; w < 3; ++w)
         for (int q = 0; q < 4; ++q) acc[q] += red[w][q][lane];
     const int pt = pt0 + li;
-    double2 *out = reinterpret_cast<double2 *>(psi);
+    typedef T pair_t __attribute__((ext_vector_type(2)));
+    pair_t *out = reinterpret_cast<pair_t *>(psi_out);
     for (int v = 0; v < 4; ++v) {
-        const int kk = k0 + 4 * v + lk;
+        const int kk = __is_same(T, double) ? k0 + 4 * v + lk : k0 + 4 * lk + v;  // result row of element v
         if (kk >= nsp) continue;
-        out[(size_t)kk * R + 4 * pt + 2 * set] = double2{acc[0][v], acc[1][v]};      // alpha
-        out[(size_t)kk * R + 4 * pt + 2 * set + 1] = double2{acc[2][v], acc[3][v]};  // beta
+        out[(size_t)kk * R + 4 * pt + 2 * set] = pair_t{acc[0][v], acc[1][v]};      // alpha
+        out[(size_t)kk * R + 4 * pt + 2 * set + 1] = pair_t{acc[2][v], acc[3][v]};  // beta
     }
 }
 
@@ -178,6 +192,11 @@ hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const dou
 
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c) {
     dim3 grid((c->nsp + 15) / 16, c->E / 16, 2);
-    spinor_gemm_kernel<<<grid, 256, 0, c->stream>>>(c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R, c->psi);
+    if (c->precision == MCMP2_FP64)
+        spinor_gemm_kernel<double><<<grid, 256, 0, c->stream>>>(c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R,
+                                                                c->psi);
+    else
+        spinor_gemm_kernel<float><<<grid, 256, 0, c->stream>>>(c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R,
+                                                               c->psi);
     return hipGetLastError();
 }

@@ -137,8 +137,8 @@ def test_invalid_arguments_raise():
                        (0, 0), 0, -1.0)
     with pytest.raises(MCMP2Error):
         _ctx(inp.with_(m=1))
-    with pytest.raises(MCMP2Error):
-        _ctx(inp, precision="fp32")
+    with pytest.raises(KeyError):
+        _ctx(inp, precision="fp8")
 
 
 def test_advance_equals_metropolis_then_sample_tau():
@@ -159,3 +159,27 @@ def test_advance_equals_metropolis_then_sample_tau():
     torch.cuda.synchronize()
     assert torch.equal(a_wk, b_wk) and torch.equal(a_w, b_w) and torch.equal(a_tau, b_tau)
     assert int(na.item()) == int(nb.item()) > 0
+
+
+def test_accumulate_is_compensated():
+    """Neumaier accumulation of many values of mixed magnitude matches
+    math.fsum (exactly rounded) to a few ulps of the total."""
+    import math
+    inp = make_inputs("C0")
+    ctx = _ctx(inp)
+    rng = np.random.default_rng(3)
+    steps = [rng.standard_normal(5) * 10.0 ** rng.integers(-8, 9, size=5) for _ in range(400)]
+    s = torch.zeros(5, dtype=torch.float64, device="cuda")
+    c = torch.zeros(5, dtype=torch.float64, device="cuda")
+    for v in steps:
+        ctx.accumulate(dev(v), s, c)
+    got = (s + c).cpu().numpy()
+    for i in range(5):
+        ref = math.fsum(v[i] for v in steps)
+        assert abs(got[i] - ref) <= 4 * np.spacing(abs(ref)) + 1e-300
+    # complex tensors are accumulated as interleaved doubles
+    z = torch.zeros(3, dtype=torch.complex128, device="cuda")
+    zc = torch.zeros(3, dtype=torch.complex128, device="cuda")
+    ctx.accumulate(dev(np.array([1 + 2j, 3 - 1j, 0.5j]), torch.complex128), z, zc)
+    ctx.accumulate(dev(np.array([1 + 2j, 3 - 1j, 0.5j]), torch.complex128), z, zc)
+    assert np.allclose((z + zc).cpu().numpy(), [2 + 4j, 6 - 2j, 1j], rtol=0, atol=0)
