@@ -4,17 +4,22 @@
 One step = one Metropolis move of all m walker pairs + inverse-CDF tau
 samples + one evaluation of the redundant-walker estimator (spinor values,
 G-/G+ for every walker pair, direct/exchange contraction, compensated sums),
-all on the GPU through libmcmp2.  Inputs are synthetic and seeded (see synth/).
+all on the GPU through libmcmp2; with gradients, also the adjoint (eps and
+coefficient gradients) and their compensated accumulation over steps.
+Inputs are synthetic and seeded (synth/).
 
-Prints one JSON line: MC steps/s, variance x time of the per-step estimates
-(blocking with N_b = 100), the roofline position of the dominant kernel
-(Green's-function GEMM + contraction, timed with HIP events on the stream it
-runs on) and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+Prints one JSON line.  The headline `value` is MC steps/s of the FP64 path
+on the chosen workload (default: the 340-spinor, 128-walker-pair FP64
+baseline workload).  Every variant (FP32 / BF16 / FP16 operands, with and
+without gradients) replays the same burned-in walker trajectory, so its
+per-step values pair with the FP64 ones: `systematic_over_sigma` is
+|mean(low - FP64)| / sigma_bar(FP64) (blocking, N_b = 100).  `roofline`
+places the dominant kernel (Green's-function GEMMs + pair contraction) on the
+FP64 MFMA roofline from HIP-event timings taken on the library's stream;
+`cpu_baseline` is the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -23,18 +28,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MC steps/s and var×time for E2(+grad), FP32/BF16 vs FP64, 1 MI355X"
+# published dense peaks of one MI355X (TFLOP/s) for the GEMM operand type
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 WORKLOADS = {
-    "C1": "plain FP64: 3 nuclei (triangle, 4.894 bohr), 200 L / 460 S Cartesian primitives, "
-          "40 occupied / 300 virtual spinors, m=128 walker pairs, 2 tau per step",
-    "C0": "tiny FP64: 2 nuclei 1.5 bohr apart, 12 L / 32 S primitives, 4 occupied / 16 virtual "
+    "C0": "tiny: 2 nuclei 1.5 bohr apart, 12 L / 32 S Cartesian primitives, 4 occupied / 16 virtual "
           "spinors, m=16 walker pairs, 1 tau per step",
+    "C1": "FP64 baseline: 3 nuclei (triangle, edge 4.894 bohr), 200 L / 460 S Cartesian primitives, "
+          "40 occupied / 300 virtual spinors, m=128 walker pairs, 2 tau per step",
+    "C3": "precision workload: 4 nuclei (tetrahedron), 600 L / 1380 S primitives, 80 occupied / 900 virtual "
+          "spinors, m=256 walker pairs, 1 tau per step",
+    "C4": "largest: 6 nuclei (octahedron), 1000 L / 2300 S primitives, 120 occupied / 1500 virtual spinors, "
+          "m=512 walker pairs, 4 tau per step",
 }
 
 
 def green_flops(m: int, n_sp: int, n_tau: int) -> float:
     """Algorithmic flops of G- and G+ over all walker pairs p < q for one
-    launch: 8x8 complex blocks, n_sp complex multiply-adds (8 flops) each."""
+    step: 8x8 complex blocks, n_sp complex multiply-adds (8 flops) each, per tau."""
     return 512.0 * (m * (m - 1) / 2.0) * n_sp * n_tau
 
 
@@ -61,9 +71,52 @@ def cpu_baseline(inp, wk0, key, delta, seconds: float):
         el = time.perf_counter() - t0
         if el >= seconds and n >= 2:
             break
-    return {"value": n / el, "unit": "MC steps/s", "cores": int(torch.get_num_threads()), "kind": "oracle",
+    return {"value": round(n / el, 4), "unit": "MC steps/s", "cores": int(torch.get_num_threads()),
+            "kind": "oracle",
             "sample": f"{n} consecutive steps (Metropolis move, tau samples, estimator) of the same workload, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s on the host"}
+
+
+def run_variant(inp, precision, grad, state, K, W, profile):
+    """Replay the burned-in trajectory for W + K steps; time the last K."""
+    import torch
+
+    from paper_2203_05632_amd import Context
+    ctx = Context.from_inputs(inp, precision=precision, want_grad=grad)
+    wk, w = state["wk"].clone(), state["w"].clone()
+    key, delta, step = state["key"], state["delta"], state["step"]
+    tau = torch.zeros(inp.n_tau, dtype=torch.float64, device="cuda")
+    hist = torch.zeros((K, inp.n_tau, 3), dtype=torch.float64, device="cuda")
+    scratch = torch.zeros((inp.n_tau, 3), dtype=torch.float64, device="cuda")
+    g = {}
+    if grad:
+        g["eps"] = torch.zeros(inp.n_sp, dtype=torch.float64, device="cuda")
+        g["c"] = torch.zeros((2, inp.n_b, inp.n_sp), dtype=torch.complex128, device="cuda")
+        g["eps_s"], g["eps_c"] = torch.zeros_like(g["eps"]), torch.zeros_like(g["eps"])
+        g["c_s"], g["c_c"] = torch.zeros_like(g["c"]), torch.zeros_like(g["c"])
+
+    def one(s, out):
+        ctx.advance(wk, w, key, s, delta, tau)          # Metropolis move + tau samples (one launch)
+        if grad:
+            ctx.step(wk, tau, out, grad_eps=g["eps"], grad_coeffs=g["c"])
+            ctx.accumulate(g["eps"], g["eps_s"], g["eps_c"])   # compensated sums over steps
+            ctx.accumulate(g["c"], g["c_s"], g["c_c"])
+        else:
+            ctx.step(wk, tau, out)                      # estimator of Eq. redundant
+
+    for i in range(W):
+        one(step + i, scratch)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile_begin(["green_contract"], K * ((inp.n_tau + 3) // 4 + 1))
+    t0 = time.perf_counter()
+    for i in range(K):
+        one(step + W + i, hist[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_end() if profile else {}
+    ctx.close()
+    return elapsed, hist.mean(dim=1)[:, 2].cpu().numpy(), prof
 
 
 def main():
@@ -73,13 +126,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--burnin", type=int, default=300, help="untimed Metropolis steps adapting delta")
     ap.add_argument("--config", default="C1", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--variant-steps", type=int, default=None, help="timed steps per variant (default: --steps)")
+    ap.add_argument("--no-variants", action="store_true", help="FP64 headline only")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0: skip)")
-    ap.add_argument("--no-kernel-timing", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build runs a single chain on one MI355X); "
-              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py measures one GPU only (one MC chain on one MI355X); --gpus {args.gpus} is not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -91,87 +144,77 @@ def main():
 
     torch.cuda.set_device(0)
     inp = make_inputs(args.config)
-    ctx = Context.from_inputs(inp, precision=args.precision)
     key = (0, 0)
     wk0 = initial_walkers(inp)
+    # burn-in on an FP64 context (walker moves do not depend on the operand precision)
+    drv = Context.from_inputs(inp)
     wk = torch.as_tensor(wk0, device="cuda")
     w = torch.zeros(inp.m, dtype=torch.float64, device="cuda")
     n_acc = torch.zeros(1, dtype=torch.int32, device="cuda")
-    tau = torch.zeros(inp.n_tau, dtype=torch.float64, device="cuda")
-    ctx.pair_weights(wk, w)
-
-    delta = 0.5
-    step = 0
-    for b in range(args.burnin // 10):
+    drv.pair_weights(wk, w)
+    delta, step = 0.5, 0
+    for _ in range(args.burnin // 10):
         n_acc.zero_()
         for _ in range(10):
-            ctx.metropolis(wk, w, key, step, delta, n_acc)
+            drv.metropolis(wk, w, key, step, delta, n_acc)
             step += 1
-        rate = n_acc.item() / (10.0 * inp.m)
-        delta *= 1.1 if rate > 0.5 else 0.9
+        delta *= 1.1 if n_acc.item() / (10.0 * inp.m) > 0.5 else 0.9
+    torch.cuda.synchronize()
+    drv.close()
+    state = {"wk": wk, "w": w, "key": key, "delta": delta, "step": step}
 
     K, W = args.steps, args.warmup
-    hist = torch.zeros((max(K, W), inp.n_tau, 3), dtype=torch.float64, device="cuda")
-
-    def one(s, out):
-        ctx.advance(wk, w, key, s, delta, tau, n_acc)   # Metropolis move + tau samples (one launch)
-        ctx.step(wk, tau, out)                          # estimator of Eq. redundant
-
-    for i in range(W):
-        one(step, hist[i])
-        step += 1
-    torch.cuda.synchronize()
-    if not args.no_kernel_timing:
-        ctx.profile_begin(["green_contract"], K)
-    t0 = time.perf_counter()
-    for i in range(K):
-        one(step, hist[i])
-        step += 1
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = {} if args.no_kernel_timing else ctx.profile_end()
-
-    vals = hist[:K].mean(dim=1).cpu().numpy()          # per-step estimate (mean over tau)
-    ms_per_step = 1e3 * elapsed / K
+    elapsed, ref_vals, prof = run_variant(inp, "fp64", False, state, K, W, profile=True)
     steps_per_s = K / elapsed
-    var_time = None
-    e2_mean = float(vals[:, 2].mean())
-    if K >= 200:
-        I, sbar = blocking(vals[:, 2], 100)
-        var_time = sbar ** 2 * elapsed
-
-    n_sp = inp.n_occ + inp.n_vir
+    sbar = blocking(ref_vals, 100)[1] if K >= 200 else None
+    flops = green_flops(inp.m, inp.n_sp, inp.n_tau)
     roofline = None
     if "green_contract" in prof:
         tot_ms, n_l = prof["green_contract"]
-        avg_s = tot_ms / n_l / 1e3
-        flops = green_flops(inp.m, n_sp, inp.n_tau)
+        avg_s = tot_ms / K / 1e3                      # per step (one launch per group of <= 4 tau)
         ach = flops / avg_s / 1e12
-        peak = PEAK_TFLOPS[args.precision]
-        roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(ach / peak, 4), "traffic": None, "kernel": "green_contract",
-                    "avg_us": round(avg_s * 1e6, 2), "flops_per_launch": flops}
+        roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                    "frac": round(ach / PEAK_TFLOPS["fp64"], 4), "traffic": None, "kernel": "green_contract",
+                    "avg_us": round(tot_ms / n_l * 1e3, 2), "launches_per_step": n_l // K,
+                    "flops_per_launch": flops / (n_l // K)}
 
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline(inp, wk0, key, delta, args.cpu_seconds)
-        cpu["value"] = round(cpu["value"], 4)
+    variants = {}
+    if not args.no_variants:
+        Kv = args.variant_steps or K
+        for prec, grad in (("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True)):
+            el, vals, vprof = run_variant(inp, prec, grad, state, Kv, W, profile=True)
+            name = prec + ("+grad" if grad else "")
+            v = {"steps_per_s": round(Kv / el, 2), "ms_per_step": round(1e3 * el / Kv, 5),
+                 "speedup_vs_fp64": round((Kv / el) / steps_per_s, 3)}
+            if "green_contract" in vprof:
+                tot_ms, n_l = vprof["green_contract"]
+                avg_s = tot_ms / Kv / 1e3
+                v["green_contract_us_per_step"] = round(avg_s * 1e6, 2)
+                v["green_tflops"] = round(flops / avg_s / 1e12, 2)
+                v["green_peak_frac"] = round(flops / avg_s / 1e12 / PEAK_TFLOPS[prec], 4)
+            if Kv == K and Kv >= 200:
+                d = vals - ref_vals
+                v["systematic_over_sigma"] = float(f"{abs(d.mean()) / sbar:.3e}")
+                v["var_x_time"] = float(f"{blocking(vals, 100)[1] ** 2 * el:.6g}")
+            variants[name] = v
 
+    cpu = cpu_baseline(inp, wk0, key, delta, args.cpu_seconds) if args.cpu_seconds > 0 else None
     out = {
         "metric": METRIC, "value": round(steps_per_s, 2), "unit": "MC steps/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
+        "warmup": W, "ms_per_step": round(1e3 * elapsed / K, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{args.config} {WORKLOADS[args.config]}", "m": inp.m, "n_tau": inp.n_tau,
                    "n_L": inp.n_L, "n_S": inp.n_S, "n_occ": inp.n_occ, "n_vir": inp.n_vir,
-                   "precision": args.precision, "grad": False},
-        "var_x_time": None if var_time is None else float(f"{var_time:.6g}"),
+                   "precision": "fp64", "grad": False},
+        "var_x_time": None if sbar is None else float(f"{sbar ** 2 * elapsed:.6g}"),
         "var_x_time_unit": "Eh^2 s",
-        "e2_mean": float(f"{e2_mean:.6g}"),
+        "e2_mean": float(f"{ref_vals.mean():.6g}"),
+        "sigma_bar": None if sbar is None else float(f"{sbar:.6g}"),
         "roofline": roofline,
+        "variants": variants,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

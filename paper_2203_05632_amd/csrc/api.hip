@@ -182,9 +182,11 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     c->precision = precision;
     c->want_grad = want_grad;
     c->lambda = lambda;
-    // low-precision operand layout: K extents (reals) padded to multiples of 32
-    c->Ko = (2 * n_occ + 31) / 32 * 32;
-    c->Ktot = c->Ko + (2 * n_vir + 31) / 32 * 32;
+    // low-precision operand layout: K extents (reals) padded to multiples of the
+    // K chunk of the low-precision Green's-function kernel (32 FP32, 64 BF16/FP16)
+    const int kq = precision == MCMP2_FP32 ? 32 : 64;
+    c->Ko = (2 * n_occ + kq - 1) / kq * kq;
+    c->Ktot = c->Ko + (2 * n_vir + kq - 1) / kq * kq;
     const size_t op_bytes = precision == MCMP2_FP32 ? 4 : 2;
 
     // N_g = sum over all pairs of weight-function Gaussians (Sec. III).

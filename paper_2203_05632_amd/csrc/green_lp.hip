@@ -10,7 +10,7 @@
 // the same range (FP16 included; terms below FP16's range flush to zero and
 // are weighted by exp(-eps tau) < 2^-24 relative to the largest).  Occupied
 // spinors fill K in [0, Ko), virtual ones [Ko, Ko + Kv), each padded with
-// zeros to a multiple of 32.
+// zeros to a multiple of the K chunk.
 //
 // With complex numbers interleaved along K, G(x, y) = sum_k s_k psi_x conj(psi_y)
 // is two real GEMMs over the same A rows:
@@ -26,7 +26,18 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-constexpr int LKC = 32;  // reals of K per LDS chunk
+// Reals of K per LDS chunk (FP32: 32 = one pass of 8 K-steps over 4 lane
+// groups; BF16/FP16: 64 = two 16x16x32 K-steps) and the padded LDS row
+// length: 16 extra bytes per row so that the 16-byte reads of 8 consecutive
+// rows fall in distinct banks.
+template <typename T>
+constexpr int lkc() {
+    return sizeof(T) == 4 ? 32 : 64;
+}
+template <typename T>
+constexpr int lrow() {
+    return lkc<T>() + 16 / (int)sizeof(T);
+}
 
 template <typename T>
 __device__ inline T to_op(double v);
@@ -89,55 +100,62 @@ struct Mfma<_Float16> {
     static constexpr int K = 32;
 };
 
-// One chunk (LKC reals of K) of this wave's 16x16 sub-tile for NT tau samples.
-// pa / pb: [NT][32 rows][LKC] operand panels (A rows of the P range, B rows of
-// the Q range).
+// One chunk of this wave's 16x16 sub-tile for NT tau samples.  pa / pb:
+// [NT][32 rows][lrow] operand panels (A rows of the P range, B rows of the Q
+// range).  Every lane reads 8 consecutive K values of its row per MFMA group:
+// FP32 lane group lk owns K = 8 lk + j of the chunk and feeds them to 8
+// successive 16x16x4 MFMAs (a dot product does not depend on how K is split
+// over the steps), so the re/im partner of every value sits in the same lane.
 template <typename T, int NT>
 __device__ inline void lp_chunk(const T *pa, const T *pb, int wp, int wq, f4v (&re)[NT], f4v (&im)[NT]) {
+    constexpr int LR = lrow<T>();
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    typedef T v8 __attribute__((ext_vector_type(8)));
     if constexpr (Mfma<T>::K == 4) {
-        const float neg = (lk & 1) ? 1.f : -1.f;  // W = (-im, re): even K takes -partner
-#pragma unroll
-        for (int ks = 0; ks < LKC; ks += 4)
-            for (int t = 0; t < NT; ++t) {
-                const float a = pa[(t * 32 + 16 * wp + li) * LKC + ks + lk];
-                const float b = pb[(t * 32 + 16 * wq + li) * LKC + ks + lk];
-                const float w = neg * __shfl_xor(b, 16, 64);
-                re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, re[t], 0, 0, 0);
-                im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w, im[t], 0, 0, 0);
-            }
-    } else {
         for (int t = 0; t < NT; ++t) {
-            typedef T v8 __attribute__((ext_vector_type(8)));
-            const v8 a = *reinterpret_cast<const v8 *>(pa + (t * 32 + 16 * wp + li) * LKC + 8 * lk);
-            const v8 b = *reinterpret_cast<const v8 *>(pb + (t * 32 + 16 * wq + li) * LKC + 8 * lk);
-            v8 w;
-            for (int c = 0; c < 4; ++c) {
-                w[2 * c] = -b[2 * c + 1];
-                w[2 * c + 1] = b[2 * c];
-            }
-            if constexpr (__is_same(T, __bf16)) {
-                re[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, re[t], 0, 0, 0);
-                im[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, im[t], 0, 0, 0);
-            } else {
-                re[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, re[t], 0, 0, 0);
-                im[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, w, im[t], 0, 0, 0);
+            const v8 a = *reinterpret_cast<const v8 *>(pa + (t * 32 + 16 * wp + li) * LR + 8 * lk);
+            const v8 b = *reinterpret_cast<const v8 *>(pb + (t * 32 + 16 * wq + li) * LR + 8 * lk);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float w = (j & 1) ? b[j - 1] : -b[j + 1];  // W = (-im, re)
+                re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], re[t], 0, 0, 0);
+                im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], w, im[t], 0, 0, 0);
             }
         }
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < lkc<T>(); ks += 32)
+            for (int t = 0; t < NT; ++t) {
+                const v8 a = *reinterpret_cast<const v8 *>(pa + (t * 32 + 16 * wp + li) * LR + ks + 8 * lk);
+                const v8 b = *reinterpret_cast<const v8 *>(pb + (t * 32 + 16 * wq + li) * LR + ks + 8 * lk);
+                v8 w;
+                for (int c = 0; c < 4; ++c) {
+                    w[2 * c] = -b[2 * c + 1];
+                    w[2 * c + 1] = b[2 * c];
+                }
+                if constexpr (__is_same(T, __bf16)) {
+                    re[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, re[t], 0, 0, 0);
+                    im[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, im[t], 0, 0, 0);
+                } else {
+                    re[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, re[t], 0, 0, 0);
+                    im[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, w, im[t], 0, 0, 0);
+                }
+            }
     }
 }
 
-// Stream K in [K_lo, K_hi) (multiples of LKC) through double-buffered LDS
+// Stream K in [K_lo, K_hi) (multiples of the chunk) through double-buffered LDS
 // panels: every thread moves 16-byte units of the NT x (A, B) panels; the next
 // chunk's loads are issued before the current chunk's MFMAs.
 template <typename T, int NT>
 __device__ inline void lp_stream(const T *__restrict__ U, int R, int Ktot, int rp, int rq, int K_lo, int K_hi, int t0,
                                  T *panels, f4v (&re)[NT], f4v (&im)[NT]) {
+    constexpr int LKC = lkc<T>(), LR = lrow<T>();
     constexpr int UPR = LKC * (int)sizeof(T) / 16;  // 16-byte units per panel row
     constexpr int UPP = 32 * UPR;                   // units per panel
     constexpr int NU = NT * 2 * UPP;                // units per chunk
     constexpr int PER = (NU + 255) / 256;           // units per thread
-    constexpr int CH = NT * 2 * 32 * LKC;           // elements of T per chunk buffer
+    constexpr int CH = NT * 2 * 32 * LR;            // elements of T per chunk buffer
     const int tid = threadIdx.x, wave = tid >> 6, wp = wave >> 1, wq = wave & 1;
     uint4 reg[PER];
     auto gload = [&](int K0) {
@@ -156,7 +174,7 @@ __device__ inline void lp_stream(const T *__restrict__ U, int R, int Ktot, int r
             const int u = tid + 256 * j;
             if (u < NU) {
                 const int t = u / (2 * UPP), ab = (u / UPP) & 1, w = u % UPP, row = w / UPR, cu = w % UPR;
-                T *dst = panels + buf * CH + ab * (NT * 32 * LKC) + (t * 32 + row) * LKC + cu * (16 / (int)sizeof(T));
+                T *dst = panels + buf * CH + ab * (NT * 32 * LR) + (t * 32 + row) * LR + cu * (16 / (int)sizeof(T));
                 *reinterpret_cast<uint4 *>(dst) = reg[j];
             }
         }
@@ -169,7 +187,7 @@ __device__ inline void lp_stream(const T *__restrict__ U, int R, int Ktot, int r
     for (int c = 0; c < n_chunks; ++c) {
         const int buf = c & 1;
         if (c + 1 < n_chunks) gload(K_lo + (c + 1) * LKC);
-        lp_chunk<T, NT>(panels + buf * CH, panels + buf * CH + NT * 32 * LKC, wp, wq, re, im);
+        lp_chunk<T, NT>(panels + buf * CH, panels + buf * CH + NT * 32 * LR, wp, wq, re, im);
         if (c + 1 < n_chunks) lstore(buf ^ 1);
         __syncthreads();
     }
@@ -182,7 +200,7 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
                                                        int n_slots, int R, int m, int t0, double *__restrict__ partial,
                                                        double2 *__restrict__ Hm, double2 *__restrict__ Hp,
                                                        double cgrad) {
-    constexpr int PANEL_BYTES = 2 * NT * 2 * 32 * LKC * (int)sizeof(T);
+    constexpr int PANEL_BYTES = 2 * NT * 2 * 32 * lrow<T>() * (int)sizeof(T);
     constexpr int EPI_BYTES = 4 * 512 * (int)sizeof(cplx);
     __shared__ __align__(16) unsigned char smem[PANEL_BYTES > EPI_BYTES ? PANEL_BYTES : EPI_BYTES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

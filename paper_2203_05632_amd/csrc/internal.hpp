@@ -51,7 +51,7 @@ struct mcmp2_ctx {
     double *hinv = nullptr;   // [m_pad] N_g / (g(r1p) g(r2p))
     double *psi = nullptr;    // [nsp][R] complex, row fastest (double2; float2 for low-precision modes)
     void *U = nullptr;        // low-precision modes: [n_tau_max][R][Ktot] scaled operands (see green_lp.hip)
-    int Ko = 0, Ktot = 0;     // K extents of the occupied segment and of all spinors (reals, multiples of 32)
+    int Ko = 0, Ktot = 0;     // K extents of the occupied segment and of all spinors (reals, multiples of the K chunk)
     double *scale = nullptr;  // [n_tau_max][nsp] exp(+eps tau) occupied, exp(-eps tau) virtual
     double *wtau = nullptr;   // [n_tau_max]
     int *tiles = nullptr;     // [n_tp][2] (P, Q), P <= Q
