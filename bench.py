@@ -27,6 +27,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad"]
 METRIC = "MC steps/s and var×time for E2(+grad), FP32/BF16 vs FP64, 1 MI355X"
 # published dense peaks of one MI355X (TFLOP/s) for the GEMM operand type
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
@@ -46,6 +47,42 @@ def green_flops(m: int, n_sp: int, n_tau: int) -> float:
     """Algorithmic flops of G- and G+ over all walker pairs p < q for one
     step: 8x8 complex blocks, n_sp complex multiply-adds (8 flops) each, per tau."""
     return 512.0 * (m * (m - 1) / 2.0) * n_sp * n_tau
+
+
+def kernel_flops(inp) -> dict:
+    """Algorithmic flops per step of each GEMM-shaped kernel (complex MAC = 8,
+    real-by-complex MAC = 4; zero walker blocks and padding not counted)."""
+    m, nsp, nb, nt = inp.m, inp.n_sp, inp.n_b, inp.n_tau
+    return {
+        "spinor_gemm": 16.0 * m * nsp * nb,          # 2m points x 4 components x nsp, real x complex over n_L or n_S
+        "green_contract": green_flops(m, nsp, nt),
+        "grad": 512.0 * m * (m - 1) * nsp * nt,      # Psibar = sum_t H_t Psi S_t, off-diagonal walker blocks
+        "coef_grad": 32.0 * m * nsp * nb,            # Cbar = X^T Psibar (both spins, re and im)
+    }
+
+
+def operand_type(prec: str, kernel: str) -> str:
+    """MFMA operand type of a kernel in a precision mode: the spinor GEMM runs
+    FP32 MFMAs in every low-precision mode; the adjoint GEMM runs BF16 in the
+    BF16 and FP16 modes and FP64 in FP32 mode; the coefficient gradient is FP64."""
+    if prec == "fp64" or kernel == "coef_grad":
+        return "fp64"
+    if kernel == "spinor_gemm":
+        return "fp32"
+    if kernel == "grad":
+        return "fp64" if prec == "fp32" else "bf16"
+    return prec
+
+
+def kernel_table(prof: dict, kflops: dict, K: int, prec: str) -> dict:
+    out = {}
+    for k, (tot_ms, _) in prof.items():
+        avg_s = tot_ms / K / 1e3
+        tf = kflops[k] / avg_s / 1e12
+        op = operand_type(prec, k)
+        out[k] = {"us_per_step": round(avg_s * 1e6, 2), "tflops": round(tf, 2), "operands": op,
+                  "peak_frac": round(tf / PEAK_TFLOPS[op], 4)}
+    return out
 
 
 def cpu_baseline(inp, wk0, key, delta, seconds: float):
@@ -108,7 +145,7 @@ def run_variant(inp, precision, grad, state, K, W, profile):
         one(step + i, scratch)
     torch.cuda.synchronize()
     if profile:
-        ctx.profile_begin(["green_contract"], K * ((inp.n_tau + 3) // 4 + 1))
+        ctx.profile_begin(PROFILED, K * len(PROFILED))
     t0 = time.perf_counter()
     for i in range(K):
         one(step + W + i, hist[i])
@@ -168,6 +205,7 @@ def main():
     steps_per_s = K / elapsed
     sbar = blocking(ref_vals, 100)[1] if K >= 200 else None
     flops = green_flops(inp.m, inp.n_sp, inp.n_tau)
+    kflops = kernel_flops(inp)
     roofline = None
     if "green_contract" in prof:
         tot_ms, n_l = prof["green_contract"]
@@ -181,17 +219,16 @@ def main():
     variants = {}
     if not args.no_variants:
         Kv = args.variant_steps or K
-        for prec, grad in (("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True)):
+        for prec, grad in (("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True),
+                           ("fp16", True)):
             el, vals, vprof = run_variant(inp, prec, grad, state, Kv, W, profile=True)
             name = prec + ("+grad" if grad else "")
             v = {"steps_per_s": round(Kv / el, 2), "ms_per_step": round(1e3 * el / Kv, 5),
                  "speedup_vs_fp64": round((Kv / el) / steps_per_s, 3)}
-            if "green_contract" in vprof:
-                tot_ms, n_l = vprof["green_contract"]
-                avg_s = tot_ms / Kv / 1e3
-                v["green_contract_us_per_step"] = round(avg_s * 1e6, 2)
-                v["green_tflops"] = round(flops / avg_s / 1e12, 2)
-                v["green_peak_frac"] = round(flops / avg_s / 1e12 / PEAK_TFLOPS[prec], 4)
+            if grad and "fp64+grad" in variants:
+                v["speedup_vs_fp64_grad"] = round((Kv / el) / variants["fp64+grad"]["steps_per_s"], 3)
+            kern = kernel_table(vprof, kflops, Kv, prec)
+            v["kernels"] = kern
             if Kv == K and Kv >= 200:
                 d = vals - ref_vals
                 v["systematic_over_sigma"] = float(f"{abs(d.mean()) / sbar:.3e}")
@@ -211,6 +248,7 @@ def main():
         "e2_mean": float(f"{ref_vals.mean():.6g}"),
         "sigma_bar": None if sbar is None else float(f"{sbar:.6g}"),
         "roofline": roofline,
+        "kernels": kernel_table(prof, kflops, K, "fp64"),
         "variants": variants,
         "cpu_baseline": cpu,
     }

@@ -201,9 +201,10 @@ enum {
     MCMP2_K_METROPOLIS = 5,     /* mcmp2_metropolis */
     MCMP2_K_SAMPLE_TAU = 6,     /* mcmp2_sample_tau */
     MCMP2_K_ADVANCE = 7,        /* mcmp2_advance */
-    MCMP2_K_GRAD = 8,           /* adjoint GEMMs: psi, eps and coefficient gradients */
+    MCMP2_K_GRAD = 8,           /* adjoint GEMM: psi and eps gradients */
     MCMP2_K_ACCUMULATE = 9,     /* mcmp2_accumulate */
-    MCMP2_NKERNELS = 10
+    MCMP2_K_COEF_GRAD = 10,     /* coefficient gradient from the psi gradient */
+    MCMP2_NKERNELS = 11
 };
 int mcmp2_profile_begin(mcmp2_ctx *ctx, uint32_t mask, int32_t max_launches);
 int mcmp2_profile_end(mcmp2_ctx *ctx, double *total_ms, int64_t *launches);

@@ -19,7 +19,7 @@ EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_set_coefficients", "mcmp2_pair_wei
            "mcmp2_advance", "mcmp2_accumulate", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_destroy",
            "mcmp2_last_error"]
 KERNELS = ["walker_weights", "step_prep", "spinor_gemm", "green_contract", "reduce", "metropolis", "sample_tau",
-           "advance", "grad", "accumulate"]
+           "advance", "grad", "accumulate", "coef_grad"]
 
 
 class Basis(ctypes.Structure):

@@ -1,0 +1,217 @@
+// Adjoint GEMM of the Green's functions with BF16 operands on MFMA (FP32
+// accumulation), used by the BF16 and FP16 modes with gradients.
+//
+// With G_t = Psi S_t Psi^H (Sec. III of the paper: G- over occupied, G+ over
+// virtual spinors; S_t = diag(exp(+eps tau_t)) or diag(exp(-eps tau_t))) and
+// H_t = Gbar_t + Gbar_t^H the adjoint blocks left by the Green's-function
+// kernel,
+//   Psibar = sum_t H_t V_t,   V_t = Psi S_t,
+//   epsbar_k = (1/2) sum_t (+-tau_t) Re(psi_k^H (H_t V_t)_k).
+// All tau samples form one GEMM with K = n_tau R: A = [H_1 .. H_T] (rows x),
+// B = [V_1; ..; V_T] stored as V_t[k][y] (y contiguous).  epsbar needs the
+// per-tau products; the kernel keeps only the running sum over tau, so at
+// each tau boundary it forms D_t[k] = Re(psi_k^H (sum_{t' <= t} H_t' V_t')_k)
+// and takes D_t - D_{t-1}.
+//
+// Complex numbers are BF16 pairs packed in 32 bits (real part low).  With
+// re/im interleaved along K, P = A B^T is two real GEMMs over the same A:
+//   Re P = A . (Vr, -Vi),   Im P = A . (Vi, Vr),
+// both B variants formed from one B fragment in registers (a sign flip of
+// the high halves, a swap of the halves).
+#include <algorithm>
+
+#include "internal.hpp"
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int AK = 32;    // complex K values (y) per LDS chunk
+constexpr int AROW = 36;  // LDS row length in 32-bit words: 32 + 4 padding (144 B)
+constexpr int ABM = 128;  // rows x per block (two row waves of 64)
+
+__device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// psi (float2 [nsp][R]) times s_t[k] -> V_t[k][y] as packed BF16 pairs.
+__global__ __launch_bounds__(256) void adj_operands_kernel(const float2 *__restrict__ psi,
+                                                           const double *__restrict__ scale, int R, int nsp,
+                                                           int n_tau, uint32_t *__restrict__ V) {
+    const size_t n = (size_t)nsp * R;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = (int)(i / R);
+    const float2 p = psi[i];
+    for (int t = 0; t < n_tau; ++t) {
+        const double s = scale[(size_t)t * nsp + k];
+        const __bf16 r = (__bf16)(float)((double)p.x * s), m = (__bf16)(float)((double)p.y * s);
+        V[(size_t)t * n + i] = (uint32_t)__builtin_bit_cast(unsigned short, r) |
+                               ((uint32_t)__builtin_bit_cast(unsigned short, m) << 16);
+    }
+}
+
+// One block: rows [x0, x0 + 128) x spinor columns [k0, k0 + 2 WN) of one
+// kind (occupied: A = H-, virtual: A = H+).  Waves (wr, wc) own 64 rows x WN
+// columns; the lane's 16x16 sub-tiles (i, j) hold rows x0 + 64 wr + 16 i +
+// 4 (l / 16) + v and column k0 + WN wc + 16 j + l % 16 in element v.
+// Work items (row tile, column tile), row-tile major, are dealt to the XCDs
+// in contiguous ranges (block b runs on XCD b % 8), so that blocks sharing
+// H rows or V columns run side by side on one L2.
+template <int WN>
+__global__ __launch_bounds__(256) void adj_lp_kernel(
+    const uint32_t *__restrict__ Hm, const uint32_t *__restrict__ Hp, const uint32_t *__restrict__ V,
+    const float2 *__restrict__ psi, const double *__restrict__ tau, int n_tau, int R, int no, int nsp,
+    int n_occ_tiles, int n_col_tiles, int n_items, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
+    constexpr int BN = 2 * WN, NJ = WN / 16;
+    constexpr int NA = ABM * (AK / 4) / 256;  // 16-byte A units per thread per chunk
+    constexpr int NB = BN * (AK / 4) / 256;   // 16-byte B units per thread per chunk
+    __shared__ __align__(16) uint32_t lds[2][(ABM + BN) * AROW];
+    __shared__ float dpart[2][BN];
+
+    const int per = (n_items + 7) / 8;
+    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= n_items) return;
+    const int rt = item / n_col_tiles, ct = item % n_col_tiles;
+    const bool occ = ct < n_occ_tiles;
+    const int k0 = occ ? BN * ct : no + BN * (ct - n_occ_tiles);
+    const int k_hi = occ ? no : nsp;
+    const uint32_t *H = occ ? Hm : Hp;
+    const int x0 = ABM * rt;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+
+    // global -> register staging: unit u = tid + 256 j covers row u / 8, words 4 (u % 8) .. + 3
+    const uint32_t *asrc[NA];
+    const uint32_t *bsrc[NB];
+    for (int j = 0; j < NA; ++j) {
+        const int u = tid + 256 * j;
+        asrc[j] = H + (size_t)min(x0 + u / 8, R - 1) * R + 4 * (u % 8);
+    }
+    for (int j = 0; j < NB; ++j) {
+        const int u = tid + 256 * j;
+        bsrc[j] = V + (size_t)min(k0 + u / 8, k_hi - 1) * R + 4 * (u % 8);
+    }
+    const size_t RR = (size_t)R * R, NR = (size_t)nsp * R;
+    const int cpt = R / AK;  // chunks per tau sample
+    const int n_chunks = n_tau * cpt;
+    u32x4 ra[NA], rb[NB];
+    auto gload = [&](int c) {
+        const int t = c / cpt, y0 = (c % cpt) * AK;
+        for (int j = 0; j < NA; ++j) ra[j] = *reinterpret_cast<const u32x4 *>(asrc[j] + t * RR + y0);
+        for (int j = 0; j < NB; ++j) rb[j] = *reinterpret_cast<const u32x4 *>(bsrc[j] + t * NR + y0);
+    };
+    auto lstore = [&](int buf) {
+        for (int j = 0; j < NA; ++j) {
+            const int u = tid + 256 * j;
+            *reinterpret_cast<u32x4 *>(&lds[buf][(u / 8) * AROW + 4 * (u % 8)]) = ra[j];
+        }
+        for (int j = 0; j < NB; ++j) {
+            const int u = tid + 256 * j;
+            *reinterpret_cast<u32x4 *>(&lds[buf][(ABM + u / 8) * AROW + 4 * (u % 8)]) = rb[j];
+        }
+    };
+
+    f4v pre[4][NJ], pim[4][NJ];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < NJ; ++j) pre[i][j] = pim[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    double d_prev = 0.0, e_acc = 0.0;  // threads tid < BN: column k0 + tid
+    const double sgn = occ ? 0.5 : -0.5;
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < n_chunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < n_chunks) gload(c + 1);
+        const uint32_t *la = &lds[buf][(64 * wr + li) * AROW + 4 * lk];
+        const uint32_t *lb = &lds[buf][(ABM + WN * wc + li) * AROW + 4 * lk];
+#pragma unroll
+        for (int ks = 0; ks < AK; ks += 16) {
+            u32x4 a[4];
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(la + 16 * i * AROW + ks);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const u32x4 b = *reinterpret_cast<const u32x4 *>(lb + 16 * j * AROW + ks);
+                u32x4 br, bi;
+                for (int q = 0; q < 4; ++q) {
+                    br[q] = b[q] ^ 0x80000000u;             // (Vr, -Vi)
+                    bi[q] = (b[q] >> 16) | (b[q] << 16);    // (Vi, Vr)
+                }
+                for (int i = 0; i < 4; ++i) {
+                    pre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[i]), as_bf16x8(br), pre[i][j], 0,
+                                                                        0, 0);
+                    pim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[i]), as_bf16x8(bi), pim[i][j], 0,
+                                                                        0, 0);
+                }
+            }
+        }
+        if (c + 1 < n_chunks) lstore(buf ^ 1);
+        if ((c + 1) % cpt == 0) {
+            // tau boundary: D_t[k] over this block's rows from the running sums
+            const int t = c / cpt;
+            for (int j = 0; j < NJ; ++j) {
+                const int k = k0 + WN * wc + 16 * j + li;
+                float d = 0.f;
+                if (k < k_hi)
+                    for (int i = 0; i < 4; ++i) {
+                        const int xb = x0 + 64 * wr + 16 * i + 4 * lk;
+                        for (int v = 0; v < 4; ++v)
+                            if (xb + v < R) {
+                                const float2 p = psi[(size_t)k * R + xb + v];
+                                d += p.x * pre[i][j][v] + p.y * pim[i][j][v];
+                            }
+                    }
+                d += __shfl_xor(d, 16, 64);
+                d += __shfl_xor(d, 32, 64);
+                if (lk == 0) dpart[wr][WN * wc + 16 * j + li] = d;
+            }
+            __syncthreads();
+            if (tid < BN) {
+                const double D = (double)dpart[0][tid] + (double)dpart[1][tid];
+                e_acc += sgn * tau[t] * (D - d_prev);
+                d_prev = D;
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int j = 0; j < NJ; ++j) {
+        const int k = k0 + WN * wc + 16 * j + li;
+        if (k >= k_hi) continue;
+        for (int i = 0; i < 4; ++i) {
+            const int xb = x0 + 64 * wr + 16 * i + 4 * lk;
+            for (int v = 0; v < 4; ++v)
+                if (xb + v < R) psibar[(size_t)k * R + xb + v] = double2{pre[i][j][v], pim[i][j][v]};
+        }
+    }
+    if (tid < BN && k0 + tid < k_hi) eps_part[(size_t)rt * nsp + k0 + tid] = e_acc;
+}
+
+template <int WN>
+hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
+    constexpr int BN = 2 * WN;
+    const int n_occ_tiles = (c->no + BN - 1) / BN, n_vir_tiles = (c->nsp - c->no + BN - 1) / BN;
+    const int n_col_tiles = n_occ_tiles + n_vir_tiles;
+    const int n_row_tiles = (c->R + ABM - 1) / ABM;
+    const int n_items = n_row_tiles * n_col_tiles;
+    const int per = (n_items + 7) / 8;
+    adj_lp_kernel<WN><<<8 * per, 256, 0, c->stream>>>(
+        reinterpret_cast<const uint32_t *>(c->Hm), reinterpret_cast<const uint32_t *>(c->Hp), c->Vt,
+        reinterpret_cast<const float2 *>(c->psi), tau, n_tau, c->R, c->no, c->nsp, n_occ_tiles, n_col_tiles, n_items,
+        reinterpret_cast<double2 *>(c->psibar), c->eps_part);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int adjoint_lp_row_tiles(const mcmp2_ctx *c) { return (c->R + ABM - 1) / ABM; }
+
+hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau) {
+    const size_t n = (size_t)c->nsp * c->R;
+    adj_operands_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+        reinterpret_cast<const float2 *>(c->psi), c->scale, c->R, c->nsp, n_tau, c->Vt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_adj_typed<64>(c, tau, n_tau);
+}

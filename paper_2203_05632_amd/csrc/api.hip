@@ -39,7 +39,7 @@ void free_ctx(mcmp2_ctx *c) {
     profiler_release(c->prof);
     void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->psi,
                     c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT,
-                    c->Hm, c->Hp, c->psibar, c->eps_part, c->U};
+                    c->Hm, c->Hp, c->psibar, c->eps_part, c->U, c->Vt, c->tiles16};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete c;
@@ -243,17 +243,30 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     c->n_slots = 4 * (int)work.size();
     TRY(dalloc(&c->tiles, 2 * (size_t)c->n_tp));
     TRY(dalloc(&c->work, work.size()));
-    TRY(dalloc(&c->partial, (size_t)n_tau_max * c->n_slots * 2));
+    std::vector<int> tiles16;
+    if (precision == MCMP2_BF16 || precision == MCMP2_FP16) {
+        c->T16 = (c->m_pad + 15) / 16;
+        build_big_tiles(c->T16, tiles16);
+        c->n_tp16 = (int)tiles16.size() / 2;
+        TRY(dalloc(&c->tiles16, tiles16.size()));
+    }
+    TRY(dalloc(&c->partial, (size_t)n_tau_max * std::max(c->n_slots, 8 * c->n_tp16) * 2));
     TRY(dalloc(&c->XT, (size_t)nb * c->E));
     if (want_grad) {
-        const size_t RR = (size_t)c->R * c->R;
-        TRY(dalloc(&c->Hm, 2 * (size_t)n_tau_max * RR));
-        TRY(dalloc(&c->Hp, 2 * (size_t)n_tau_max * RR));
+        // adjoint blocks: FP64 complex (FP64, FP32 modes) or packed BF16 pairs (BF16, FP16 modes)
+        const bool h16 = precision == MCMP2_BF16 || precision == MCMP2_FP16;
+        const size_t hbytes = (h16 ? 4 : 16) * (size_t)n_tau_max * c->R * c->R;
+        unsigned char *hm = nullptr, *hp = nullptr;
+        TRY(dalloc(&hm, hbytes));
+        c->Hm = reinterpret_cast<double *>(hm);
+        TRY(dalloc(&hp, hbytes));
+        c->Hp = reinterpret_cast<double *>(hp);
         TRY(dalloc(&c->psibar, 2 * (size_t)nsp * c->R));
         TRY(dalloc(&c->eps_part, (size_t)(c->R / 32) * nsp));
+        if (h16) TRY(dalloc(&c->Vt, (size_t)n_tau_max * nsp * c->R));
         // blocks that are never written (p = q, padding walkers) must read as zero
-        TRY(check_hip(hipMemset(c->Hm, 0, 2 * sizeof(double) * n_tau_max * RR), "hipMemset"));
-        TRY(check_hip(hipMemset(c->Hp, 0, 2 * sizeof(double) * n_tau_max * RR), "hipMemset"));
+        TRY(check_hip(hipMemset(c->Hm, 0, hbytes), "hipMemset"));
+        TRY(check_hip(hipMemset(c->Hp, 0, hbytes), "hipMemset"));
     }
 
     auto up = [&](void *dst, const void *src, size_t bytes) {
@@ -277,6 +290,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(up(c->eps, eps, sizeof(double) * nsp));
     TRY(up(c->tiles, tiles.data(), tiles.size() * sizeof(int)));
     TRY(up(c->work, work.data(), work.size() * sizeof(int)));
+    if (c->n_tp16) TRY(up(c->tiles16, tiles16.data(), tiles16.size() * sizeof(int)));
     // padding rows / points stay zero for the lifetime of the context
     TRY(check_hip(hipMemset(c->XT, 0, sizeof(double) * (size_t)nb * c->E), "hipMemset"));
     TRY(check_hip(hipMemset(c->psi, 0, 2 * sizeof(double) * (size_t)nsp * c->R), "hipMemset"));
@@ -314,7 +328,10 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
     if ((rc = timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); })) != MCMP2_OK)
         return rc;
     if (!grad) return MCMP2_OK;
-    return timed(c, MCMP2_K_GRAD, "grad", [&] { return launch_grad(c, tau, n_tau, grad_eps, grad_coeffs); });
+    if ((rc = timed(c, MCMP2_K_GRAD, "adjoint", [&] { return launch_adjoint(c, tau, n_tau, grad_eps); })) != MCMP2_OK)
+        return rc;
+    if (!grad_coeffs) return MCMP2_OK;
+    return timed(c, MCMP2_K_COEF_GRAD, "coef_grad", [&] { return launch_coef_grad(c, grad_coeffs); });
 }
 
 extern "C" int mcmp2_set_coefficients(mcmp2_ctx *c, const double *coeffs, const double *eps) {

@@ -20,26 +20,33 @@ __device__ inline cplx shfl_xor_c(cplx a, int mask) {
     return {__shfl_xor(a.re, mask, 64), __shfl_xor(a.im, mask, 64)};
 }
 
+// Adjoint-block element stores: FP64 complex, or a BF16 pair packed in 32
+// bits (real part in the low half), rounded to nearest even.
+__device__ inline void h_store(double2 *H, size_t i, double re, double im) { H[i] = double2{re, im}; }
+__device__ inline void h_store(uint32_t *H, size_t i, double re, double im) {
+    const __bf16 r = (__bf16)(float)re, m = (__bf16)(float)im;
+    H[i] = (uint32_t)__builtin_bit_cast(unsigned short, r) | ((uint32_t)__builtin_bit_cast(unsigned short, m) << 16);
+}
 
-// One wave, one tau sample.  Gm / Gp: this wave's 16x16 sub-tiles of G- and
-// G+ (complex FP64, row-major, rows 8 pp + 4 e + i of block-tile row PT,
-// columns 8 qq + 4 f + j of block-tile column QT; the wave's sub-tile origin
-// is (wp, wq) = (wave >> 1, wave & 1)).  16 lanes per walker pair: (pp, qq) =
-// walker offsets in the sub-tile, (a, b) = 4x4 matrix indices of the lane.
-// Writes the wave's direct and exchange sums to out[0], out[1] and, with
-// GRAD, the pairs' adjoint blocks into Hm / Hp (R x R complex, this tau).
-template <bool GRAD>
-__device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, int QT, int m,
-                                      const double *__restrict__ hinv, double wt, double cgrad, int R,
-                                      double *__restrict__ out, double2 *__restrict__ Hm, double2 *__restrict__ Hp) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wp = wave >> 1, wq = wave & 1;
-    const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
+
+__device__ inline cplx to_c(const cplx &v) { return v; }
+__device__ inline cplx to_c(const float2 &v) { return {(double)v.x, (double)v.y}; }
+
+// One walker pair (p, q) per 16 lanes (lane & 15 = 4 a + b: indices of the
+// 4x4 blocks).  Gm / Gp: element (e, i; f, j) of the pair's G- / G+ block
+// (rows 8 p + 4 e + i, columns 8 q + 4 f + j) at [(4 e + i) ld + 4 f + j]
+// (complex FP64 or FP32; the arithmetic is FP64).  Returns the pair's
+// weighted direct and exchange terms (zero unless ok) in every lane of the
+// group and, with GRAD, writes the pair's adjoint blocks and their
+// Hermitian partners into Hm / Hp (R x R, this tau; HT = double2, or
+// uint32_t for BF16 pairs).
+template <bool GRAD, typename HT, typename GT>
+__device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, int q, bool ok,
+                                     const double *__restrict__ hinv, double wt, double cgrad, int R, double &dir,
+                                     double &exc, HT *__restrict__ Hm, HT *__restrict__ Hp) {
+    const int lane = threadIdx.x & 63;
     const int a = (lane & 15) >> 2, b = lane & 3;
-    const int p = kTileWalkers * PT + 2 * wp + pp, q = kTileWalkers * QT + 2 * wq + qq;
-    const bool pair_ok = p < q && q < m;
-    // block (e, f) of the pair: rows 8 pp + 4 e + i, cols 8 qq + 4 f + j
-#define GB(G, e, f, i, j) G[(8 * pp + 4 * (e) + (i)) * 16 + 8 * qq + 4 * (f) + (j)]
+#define GB(G, e, f, i, j) to_c(G[(4 * (e) + (i)) * ld + 4 * (f) + (j)])
     cplx t1 = cmulc(GB(Gm, 0, 0, a, b), GB(Gp, 0, 0, a, b));
     cplx t2 = cmulc(GB(Gm, 1, 1, a, b), GB(Gp, 1, 1, a, b));
     cplx m1 = {0.0, 0.0}, m2 = {0.0, 0.0};
@@ -53,8 +60,8 @@ __device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, in
         t2 = cadd(t2, shfl_xor_c(t2, mask));
         xt = cadd(xt, shfl_xor_c(xt, mask));
     }
-    double dir = 0.0, exc = 0.0;
-    if (pair_ok) {
+    dir = exc = 0.0;
+    if (ok) {
         const double W = hinv[p] * hinv[q] / wt;
         const cplx D = cmul(t1, t2);
         dir = -0.5 * D.re * W;
@@ -68,14 +75,29 @@ __device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, in
             //   H+(1,4) = -c A13 P23^H A24            H+(2,3) = -c A24 P14^H A13
             // Lane (a, b) forms element [a][b] of each block.
             const double cw = cgrad * W;
+            // The triple products as (X Y^H) Z: lane (a, b) forms [X Y^H]_{ab}
+            // (four terms), then row a of it is gathered from lanes 4 a + l of
+            // the pair's group for the product with Z.
+            cplx x13 = {0.0, 0.0}, x24 = {0.0, 0.0}, x14 = {0.0, 0.0}, x23 = {0.0, 0.0};
+            for (int k = 0; k < 4; ++k) {
+                x13 = cadd(x13, cmul(GB(Gp, 0, 1, a, k), conjc(GB(Gm, 1, 1, b, k))));  // P14 A24^H
+                x24 = cadd(x24, cmul(GB(Gp, 1, 0, a, k), conjc(GB(Gm, 0, 0, b, k))));  // P23 A13^H
+                x14 = cadd(x14, cmul(GB(Gm, 0, 0, a, k), conjc(GB(Gp, 1, 0, b, k))));  // A13 P23^H
+                x23 = cadd(x23, cmul(GB(Gm, 1, 1, a, k), conjc(GB(Gp, 0, 1, b, k))));  // A24 P14^H
+            }
             cplx s13 = {0.0, 0.0}, s24 = {0.0, 0.0}, s14 = {0.0, 0.0}, s23 = {0.0, 0.0};
-            for (int k = 0; k < 4; ++k)
-                for (int l = 0; l < 4; ++l) {
-                    s13 = cadd(s13, cmul(cmul(GB(Gp, 0, 1, a, k), conjc(GB(Gm, 1, 1, l, k))), GB(Gp, 1, 0, l, b)));
-                    s24 = cadd(s24, cmul(cmul(GB(Gp, 1, 0, a, k), conjc(GB(Gm, 0, 0, l, k))), GB(Gp, 0, 1, l, b)));
-                    s14 = cadd(s14, cmul(cmul(GB(Gm, 0, 0, a, k), conjc(GB(Gp, 1, 0, l, k))), GB(Gm, 1, 1, l, b)));
-                    s23 = cadd(s23, cmul(cmul(GB(Gm, 1, 1, a, k), conjc(GB(Gp, 0, 1, l, k))), GB(Gm, 0, 0, l, b)));
-                }
+            const int row0 = lane & ~3;
+            for (int l = 0; l < 4; ++l) {
+                const int src = row0 | l;
+                const cplx y13 = {__shfl(x13.re, src, 64), __shfl(x13.im, src, 64)};
+                const cplx y24 = {__shfl(x24.re, src, 64), __shfl(x24.im, src, 64)};
+                const cplx y14 = {__shfl(x14.re, src, 64), __shfl(x14.im, src, 64)};
+                const cplx y23 = {__shfl(x23.re, src, 64), __shfl(x23.im, src, 64)};
+                s13 = cadd(s13, cmul(y13, GB(Gp, 1, 0, l, b)));  // (P14 A24^H) P23
+                s24 = cadd(s24, cmul(y24, GB(Gp, 0, 1, l, b)));  // (P23 A13^H) P14
+                s14 = cadd(s14, cmul(y14, GB(Gm, 1, 1, l, b)));  // (A13 P23^H) A24
+                s23 = cadd(s23, cmul(y23, GB(Gm, 0, 0, l, b)));  // (A24 P14^H) A13
+            }
             const cplx p13 = GB(Gp, 0, 0, a, b), p24 = GB(Gp, 1, 1, a, b);
             const cplx a13 = GB(Gm, 0, 0, a, b), a24 = GB(Gm, 1, 1, a, b);
             const cplx hm13 = cscale(csub(cmul(t2, p13), s13), cw);
@@ -85,9 +107,9 @@ __device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, in
             const cplx hp14 = cscale(s14, -cw);
             const cplx hp23 = cscale(s23, -cw);
             const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
-            auto put = [&](double2 *H, size_t r, size_t cc, cplx v) {
-                H[r * R + cc] = double2{v.re, v.im};
-                H[cc * R + r] = double2{v.re, -v.im};  // Hermitian partner block (q, p)
+            auto put = [&](HT *H, size_t r, size_t cc, cplx v) {
+                h_store(H, r * R + cc, v.re, v.im);
+                h_store(H, cc * R + r, v.re, -v.im);  // Hermitian partner block (q, p)
             };
             put(Hm, r1, c3, hm13);
             put(Hm, r2, c4, hm24);
@@ -98,6 +120,25 @@ __device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, in
         }
     }
 #undef GB
+}
+
+// One wave, one tau sample.  Gm / Gp: this wave's 16x16 sub-tiles of G- and
+// G+ (complex FP64, row-major, rows 8 pp + 4 e + i of block-tile row PT,
+// columns 8 qq + 4 f + j of block-tile column QT; the wave's sub-tile origin
+// is (wp, wq) = (wave >> 1, wave & 1)).  16 lanes per walker pair: (pp, qq) =
+// walker offsets in the sub-tile.  Writes the wave's direct and exchange
+// sums to out[0], out[1] and, with GRAD, the pairs' adjoint blocks.
+template <bool GRAD, typename HT>
+__device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, int QT, int m,
+                                      const double *__restrict__ hinv, double wt, double cgrad, int R,
+                                      double *__restrict__ out, HT *__restrict__ Hm, HT *__restrict__ Hp) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wp = wave >> 1, wq = wave & 1;
+    const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
+    const int p = kTileWalkers * PT + 2 * wp + pp, q = kTileWalkers * QT + 2 * wq + qq;
+    double dir, exc;
+    contract_pair<GRAD, HT>(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv,
+                            wt, cgrad, R, dir, exc, Hm, Hp);
     // pairs of this wave summed in a fixed order (lanes 0, 16, 32, 48)
     const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
                  d3 = __shfl(dir, 48, 64);

@@ -56,20 +56,28 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
 
     // cooperative chunk loads: element e in {tid, tid + 256} -> (row = e / 16, y = e % 16)
     const int e0 = tid, e1 = tid + 256;
-    double2 ra[NT][2], rb[2];
-    auto gload = [&](int y0) {
+    // staging registers as ext_vector_type (HIP's double2 struct would be kept in scratch memory)
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    d2v ra[NT][2], rb[2];
+    auto gload = [&](int y0) __attribute__((always_inline)) {
+#pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int e = j ? e1 : e0, r = e >> 4, y = y0 + (e & 15);
-            for (int t = 0; t < NT; ++t) ra[t][j] = H[(size_t)(t0 + t) * RR + (size_t)(x0 + r) * R + y];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                ra[t][j] = *reinterpret_cast<const d2v *>(&H[(size_t)(t0 + t) * RR + (size_t)(x0 + r) * R + y]);
             const int kk = k0 + r;
-            rb[j] = kk < k_hi ? to_d2(psi[(size_t)kk * R + y]) : double2{0.0, 0.0};
+            const double2 pv = kk < k_hi ? to_d2(psi[(size_t)kk * R + y]) : double2{0.0, 0.0};
+            rb[j] = d2v{pv.x, pv.y};
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int e = j ? e1 : e0, r = e >> 4, y = e & 15;
-            for (int t = 0; t < NT; ++t) pa[buf][t][y][r] = ra[t][j];
-            pb[buf][y][r] = rb[j];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) *reinterpret_cast<d2v *>(&pa[buf][t][y][r]) = ra[t][j];
+            *reinterpret_cast<d2v *>(&pb[buf][y][r]) = rb[j];
         }
     };
 
@@ -215,14 +223,14 @@ hipError_t launch_grad_gemm(const mcmp2_ctx *c, const double *tau, int n_tau, in
 
 }  // namespace
 
-hipError_t launch_grad(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps, double *grad_coeffs) {
+hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps) {
     const int n_occ_tiles = (c->no + 31) / 32, n_vir_tiles = (c->nsp - c->no + 31) / 32;
-    const int n_rowtiles = c->R / 32;
-    double2 *psibar = reinterpret_cast<double2 *>(c->psibar);
+    const bool h16 = c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16;
+    const int n_rowtiles = h16 ? adjoint_lp_row_tiles(c) : c->R / 32;
     {
-        hipError_t e = c->precision == MCMP2_FP64
-                           ? launch_grad_gemm<double2>(c, tau, n_tau, n_occ_tiles, n_vir_tiles)
-                           : launch_grad_gemm<float2>(c, tau, n_tau, n_occ_tiles, n_vir_tiles);
+        hipError_t e = c->precision == MCMP2_FP64 ? launch_grad_gemm<double2>(c, tau, n_tau, n_occ_tiles, n_vir_tiles)
+                       : h16                     ? launch_adjoint_lp(c, tau, n_tau)
+                                                 : launch_grad_gemm<float2>(c, tau, n_tau, n_occ_tiles, n_vir_tiles);
         if (e != hipSuccess) return e;
     }
     if (grad_eps) {
@@ -230,7 +238,12 @@ hipError_t launch_grad(const mcmp2_ctx *c, const double *tau, int n_tau, double 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (grad_coeffs) {
+    return hipSuccess;
+}
+
+hipError_t launch_coef_grad(const mcmp2_ctx *c, double *grad_coeffs) {
+    const double2 *psibar = reinterpret_cast<const double2 *>(c->psibar);
+    {
         const int n_L_tiles = (c->nL + 15) / 16, n_S_tiles = (c->nS + 15) / 16;
         dim3 g2(n_L_tiles + n_S_tiles, (c->nsp + 15) / 16);
         coef_grad_kernel<<<g2, 256, 0, c->stream>>>(c->XT, psibar, c->E, 2 * c->m, c->nb, c->nL, c->nsp, c->R,

@@ -227,6 +227,7 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
     cplx *Gm = reinterpret_cast<cplx *>(&panel[0][0][0][0]) + wave * 512;
     cplx *Gp = Gm + 256;
     const int slot = 4 * blockIdx.x + wave;
+#pragma unroll  // constant indices keep the accumulators in registers
     for (int t = 0; t < NT; ++t) {
         for (int v = 0; v < 4; ++v) {
             const int i = 4 * v + lk;  // MFMA f64 result row of element v
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
             Gp[i * 16 + li] = {gp_re[t][v], gp_im[t][v]};
         }
         __syncthreads();
-        contract_pairs<GRAD>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
+        contract_pairs<GRAD, double2>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
                              partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
                              GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
                              GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
@@ -323,6 +324,7 @@ hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
 
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out) {
     const double inv_pairs = 1.0 / (0.5 * (double)c->m * (double)(c->m - 1));
-    reduce_kernel<<<n_tau, 256, 0, c->stream>>>(c->partial, c->n_slots, inv_pairs, e2_out);
+    const int n_slots = green_big_selected(c, n_tau) ? 8 * c->n_tp16 : c->n_slots;
+    reduce_kernel<<<n_tau, 256, 0, c->stream>>>(c->partial, n_slots, inv_pairs, e2_out);
     return hipGetLastError();
 }

@@ -17,12 +17,14 @@
 //   Re G = U_x . U_y,   Im G = U_x . W_y,  W = (-im, re) pairs of U_y,
 // W being formed from the B operand in registers.
 #include <algorithm>
+#include <type_traits>
 
 #include "contract.hpp"
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -107,7 +109,7 @@ struct Mfma<_Float16> {
 // successive 16x16x4 MFMAs (a dot product does not depend on how K is split
 // over the steps), so the re/im partner of every value sits in the same lane.
 template <typename T, int NT>
-__device__ inline void lp_chunk(const T *pa, const T *pb, int wp, int wq, f4v (&re)[NT], f4v (&im)[NT]) {
+__device__ __attribute__((always_inline)) inline void lp_chunk(const T *pa, const T *pb, int wp, int wq, f4v (&re)[NT], f4v (&im)[NT]) {
     constexpr int LR = lrow<T>();
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     typedef T v8 __attribute__((ext_vector_type(8)));
@@ -148,7 +150,7 @@ __device__ inline void lp_chunk(const T *pa, const T *pb, int wp, int wq, f4v (&
 // panels: every thread moves 16-byte units of the NT x (A, B) panels; the next
 // chunk's loads are issued before the current chunk's MFMAs.
 template <typename T, int NT>
-__device__ inline void lp_stream(const T *__restrict__ U, int R, int Ktot, int rp, int rq, int K_lo, int K_hi, int t0,
+__device__ __attribute__((always_inline)) inline void lp_stream(const T *__restrict__ U, int R, int Ktot, int rp, int rq, int K_lo, int K_hi, int t0,
                                  T *panels, f4v (&re)[NT], f4v (&im)[NT]) {
     constexpr int LKC = lkc<T>(), LR = lrow<T>();
     constexpr int UPR = LKC * (int)sizeof(T) / 16;  // 16-byte units per panel row
@@ -157,25 +159,27 @@ __device__ inline void lp_stream(const T *__restrict__ U, int R, int Ktot, int r
     constexpr int PER = (NU + 255) / 256;           // units per thread
     constexpr int CH = NT * 2 * 32 * LR;            // elements of T per chunk buffer
     const int tid = threadIdx.x, wave = tid >> 6, wp = wave >> 1, wq = wave & 1;
-    uint4 reg[PER];
-    auto gload = [&](int K0) {
+    // Loads are branch-free (a thread past the last unit re-reads the last
+    // one) and the loops unrolled, so the staging registers stay registers.
+    u32x4 reg[PER];  // ext_vector_type: HIP's uint4 struct defeats scalar replacement
+    auto gload = [&](int K0) __attribute__((always_inline)) {
+#pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int u = tid + 256 * j;
-            if (u < NU) {
-                const int t = u / (2 * UPP), ab = (u / UPP) & 1, w = u % UPP, row = w / UPR, cu = w % UPR;
-                const T *src = U + (size_t)(t0 + t) * R * Ktot + (size_t)((ab ? rq : rp) + row) * Ktot + K0 +
-                               cu * (16 / (int)sizeof(T));
-                reg[j] = *reinterpret_cast<const uint4 *>(src);
-            }
+            const int u = min(tid + 256 * j, NU - 1);
+            const int t = u / (2 * UPP), ab = (u / UPP) & 1, w = u % UPP, row = w / UPR, cu = w % UPR;
+            const T *src = U + (size_t)(t0 + t) * R * Ktot + (size_t)((ab ? rq : rp) + row) * Ktot + K0 +
+                           cu * (16 / (int)sizeof(T));
+            reg[j] = *reinterpret_cast<const u32x4 *>(src);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int u = tid + 256 * j;
             if (u < NU) {
                 const int t = u / (2 * UPP), ab = (u / UPP) & 1, w = u % UPP, row = w / UPR, cu = w % UPR;
                 T *dst = panels + buf * CH + ab * (NT * 32 * LR) + (t * 32 + row) * LR + cu * (16 / (int)sizeof(T));
-                *reinterpret_cast<uint4 *>(dst) = reg[j];
+                *reinterpret_cast<u32x4 *>(dst) = reg[j];
             }
         }
     };
@@ -193,13 +197,14 @@ __device__ inline void lp_stream(const T *__restrict__ U, int R, int Ktot, int r
     }
 }
 
-template <typename T, int NT, bool GRAD>
+// HT: element type of the adjoint blocks (FP64 complex with FP32 operands,
+// packed BF16 pairs with BF16 / FP16 operands).
+template <typename T, int NT, bool GRAD, typename HT>
 __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, int Ko, int Ktot,
                                                        const double *__restrict__ wtau, const double *__restrict__ hinv,
                                                        const int *__restrict__ tiles, const int *__restrict__ work,
                                                        int n_slots, int R, int m, int t0, double *__restrict__ partial,
-                                                       double2 *__restrict__ Hm, double2 *__restrict__ Hp,
-                                                       double cgrad) {
+                                                       HT *__restrict__ Hm, HT *__restrict__ Hp, double cgrad) {
     constexpr int PANEL_BYTES = 2 * NT * 2 * 32 * lrow<T>() * (int)sizeof(T);
     constexpr int EPI_BYTES = 4 * 512 * (int)sizeof(cplx);
     __shared__ __align__(16) unsigned char smem[PANEL_BYTES > EPI_BYTES ? PANEL_BYTES : EPI_BYTES];
@@ -225,6 +230,7 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
 
     cplx *Gm = reinterpret_cast<cplx *>(smem) + wave * 512;
     cplx *Gp = Gm + 256;
+#pragma unroll  // constant indices keep the accumulators in registers
     for (int t = 0; t < NT; ++t) {
         for (int v = 0; v < 4; ++v) {
             const int i = 4 * lk + v;  // MFMA f32 result row of element v
@@ -232,12 +238,167 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
             Gp[i * 16 + li] = {(double)gp_re[t][v], (double)gp_im[t][v]};
         }
         __syncthreads();
-        contract_pairs<GRAD>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
+        contract_pairs<GRAD, HT>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
                              partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
                              GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
                              GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 / FP16 operands, large problems: one block of 8 waves per (tau, tile
+// pair) with 128 x 128 block tiles (16 x 16 walkers), G- and G+ both kept in
+// registers (each wave: 64 rows x 32 columns of each).  Work items
+// (tau-major, tile pairs in 4 x 8 patches) are dealt to the XCDs in
+// contiguous ranges (block b runs on XCD b % 8), so that blocks of one XCD
+// share operand rows in its L2.  The epilogue stages each wave's G rows in
+// LDS (FP32) two walkers at a time and runs the FP64 pair contraction.
+constexpr int BW = 16;          // walkers per big tile side
+constexpr int BT = 8 * BW;      // rows per big tile side
+constexpr int BKW = 32;         // 32-bit words (one complex operand each) per row per chunk
+constexpr int BROW = BKW + 4;   // padded LDS row in words (144 B)
+
+template <typename T>
+__device__ inline f4v mfma_pair(u32x4 a, u32x4 b, f4v c) {
+    if constexpr (__is_same(T, __bf16))
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                       0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                      0, 0);
+}
+
+template <typename T, bool GRAD>
+__global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restrict__ U, int Kow, int Ktw,
+                                                        const double *__restrict__ wtau,
+                                                        const double *__restrict__ hinv,
+                                                        const int *__restrict__ tiles16, int n_tp, int n_items, int R,
+                                                        int m, double *__restrict__ partial,
+                                                        uint32_t *__restrict__ Hm, uint32_t *__restrict__ Hp,
+                                                        double cgrad) {
+    constexpr int STAGE = 2 * BT * BROW;  // words per stage: A rows then B rows
+    __shared__ __align__(16) uint32_t lds[2 * STAGE];
+    const int per = (n_items + 7) / 8;
+    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= n_items) return;
+    const int t = item / n_tp, tp = item % n_tp;
+    const int P = tiles16[2 * tp], Q = tiles16[2 * tp + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 2, wc = wave & 3, li = lane & 15, lk = lane >> 4;
+    const uint32_t *Ut = U + (size_t)t * R * Ktw;
+
+    // staging unit u = tid + 512 j: row u / 8 of the stage (A: rows of P, B: rows of Q), words 4 (u % 8) .. + 3
+    const uint32_t *src[4];
+    for (int j = 0; j < 4; ++j) {
+        const int u = tid + 512 * j, row = u >> 3;
+        const int grow = row < BT ? BT * P + row : BT * Q + (row - BT);
+        src[j] = Ut + (size_t)min(grow, R - 1) * Ktw + 4 * (u & 7);
+    }
+    u32x4 rg[4];
+    auto gload = [&](int w0) __attribute__((always_inline)) {
+        for (int j = 0; j < 4; ++j) rg[j] = *reinterpret_cast<const u32x4 *>(src[j] + w0);
+    };
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+        for (int j = 0; j < 4; ++j) {
+            const int u = tid + 512 * j;
+            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + (u >> 3) * BROW + 4 * (u & 7)]) = rg[j];
+        }
+    };
+    f4v gm_re[4][2], gm_im[4][2], gp_re[4][2], gp_im[4][2];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 2; ++j) gm_re[i][j] = gm_im[i][j] = gp_re[i][j] = gp_im[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    // G(x, y) = sum_k U_x conj(U_y): Re = U_x . U_y, Im = U_x . (-Im U_y, Re U_y)
+    auto chunk = [&](int buf, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
+        const uint32_t *la = &lds[buf * STAGE + (64 * wr + li) * BROW + 4 * lk];
+        const uint32_t *lb = &lds[buf * STAGE + (BT + 32 * wc + li) * BROW + 4 * lk];
+#pragma unroll
+        for (int ks = 0; ks < BKW; ks += 16) {
+            u32x4 a[4];
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(la + 16 * i * BROW + ks);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const u32x4 b = *reinterpret_cast<const u32x4 *>(lb + 16 * j * BROW + ks);
+                u32x4 w;
+                for (int q = 0; q < 4; ++q) w[q] = ((b[q] >> 16) | (b[q] << 16)) ^ 0x8000u;
+                for (int i = 0; i < 4; ++i) {
+                    re[i][j] = mfma_pair<T>(a[i], b, re[i][j]);
+                    im[i][j] = mfma_pair<T>(a[i], w, im[i][j]);
+                }
+            }
+        }
+    };
+    auto stream = [&](int w_lo, int w_hi, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
+        const int n = (w_hi - w_lo) / BKW;
+        if (n == 0) return;
+        gload(w_lo);
+        lstore(0);
+        __syncthreads();
+        for (int c = 0; c < n; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < n) gload(w_lo + (c + 1) * BKW);
+            chunk(buf, re, im);
+            if (c + 1 < n) lstore(buf ^ 1);
+            __syncthreads();
+        }
+    };
+    stream(0, Kow, gm_re, gm_im);
+    stream(Kow, Ktw, gp_re, gp_im);
+
+    // epilogue: wave-private G rows in LDS, 16 rows (two walkers) x 32 columns (four walkers) per pass
+    float2 *Gm = reinterpret_cast<float2 *>(lds) + wave * 1024;
+    float2 *Gp = Gm + 512;
+    uint32_t *Hm_t = GRAD ? Hm + (size_t)t * R * R : nullptr;
+    uint32_t *Hp_t = GRAD ? Hp + (size_t)t * R * R : nullptr;
+    const double wt = wtau[t];
+    double dsum = 0.0, xsum = 0.0;
+#pragma unroll  // constant indices keep the accumulators in registers
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) {
+                const int e = (4 * lk + v) * 32 + 16 * j + li;  // MFMA result row 4 lk + v, column 16 j + li
+                Gm[e] = float2{gm_re[i][j][v], gm_im[i][j][v]};
+                Gp[e] = float2{gp_re[i][j][v], gp_im[i][j][v]};
+            }
+        __syncthreads();
+        for (int r = 0; r < 2; ++r) {
+            const int pi = 4 * r + lk, pr = pi >> 2, qc = pi & 3;
+            const int p = BW * P + 8 * wr + 2 * i + pr, q = BW * Q + 4 * wc + qc;
+            double dir, exc;
+            contract_pair<GRAD, uint32_t>(Gm + 8 * pr * 32 + 8 * qc, Gp + 8 * pr * 32 + 8 * qc, 32, p, q,
+                                          p < q && q < m, hinv, wt, cgrad, R, dir, exc, Hm_t, Hp_t);
+            const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
+                         d3 = __shfl(dir, 48, 64);
+            const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
+                         x3 = __shfl(exc, 48, 64);
+            dsum += ((d0 + d1) + d2) + d3;
+            xsum += ((x0 + x1) + x2) + x3;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        double *out = partial + ((size_t)item * 8 + wave) * 2;
+        out[0] = dsum;
+        out[1] = xsum;
+    }
+}
+
+template <typename T>
+hipError_t launch_big_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
+    const int n_items = c->n_tp16 * n_tau;
+    const int per = (n_items + 7) / 8;
+    const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
+    const uint32_t *U = reinterpret_cast<const uint32_t *>(c->U);
+    uint32_t *Hm = reinterpret_cast<uint32_t *>(c->Hm), *Hp = reinterpret_cast<uint32_t *>(c->Hp);
+    if (grad)
+        green_big_kernel<T, true><<<8 * per, 512, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau, c->hinv,
+                                                                  c->tiles16, c->n_tp16, n_items, c->R, c->m,
+                                                                  c->partial, Hm, Hp, cgrad);
+    else
+        green_big_kernel<T, false><<<8 * per, 512, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau, c->hinv,
+                                                                   c->tiles16, c->n_tp16, n_items, c->R, c->m,
+                                                                   c->partial, nullptr, nullptr, 0.0);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -248,19 +409,22 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
                                                     c->nsp, c->no, c->Ko, c->Ktot, U);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if constexpr (sizeof(T) == 2)
+        if (green_big_selected(c, n_tau)) return launch_big_typed<T>(c, n_tau, grad);
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
-    double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
+    using HT = std::conditional_t<sizeof(T) == 4, double2, uint32_t>;
+    HT *Hm = reinterpret_cast<HT *>(c->Hm), *Hp = reinterpret_cast<HT *>(c->Hp);
     const int nblocks = c->n_slots / 4;
     constexpr int NTMAX = sizeof(T) == 4 ? 2 : 4;  // FP32 panels are twice as large
     for (int t0 = 0; t0 < n_tau; t0 += NTMAX) {
         const int nt = std::min(NTMAX, n_tau - t0);
 #define LP_LAUNCH(NTV)                                                                                            \
     if (grad)                                                                                                     \
-        green_lp_kernel<T, NTV, true><<<nblocks, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,       \
+        green_lp_kernel<T, NTV, true, HT><<<nblocks, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,       \
                                                                       c->tiles, c->work, c->n_slots, c->R, c->m, \
                                                                       t0, c->partial, Hm, Hp, cgrad);            \
     else                                                                                                          \
-        green_lp_kernel<T, NTV, false><<<nblocks, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,      \
+        green_lp_kernel<T, NTV, false, HT><<<nblocks, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,      \
                                                                        c->tiles, c->work, c->n_slots, c->R,      \
                                                                        c->m, t0, c->partial, nullptr, nullptr,   \
                                                                        0.0)
@@ -278,6 +442,21 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
 }
 
 }  // namespace
+
+bool green_big_selected(const mcmp2_ctx *c, int n_tau) {
+    return (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) && c->n_tp16 * n_tau >= 256;
+}
+
+void build_big_tiles(int T16, std::vector<int> &tiles) {
+    tiles.clear();
+    for (int Pb = 0; Pb < T16; Pb += 4)
+        for (int Qb = Pb / 8 * 8; Qb < T16; Qb += 8)
+            for (int P = Pb; P < std::min(Pb + 4, T16); ++P)
+                for (int Q = std::max(P, Qb); Q < std::min(Qb + 8, T16); ++Q) {
+                    tiles.push_back(P);
+                    tiles.push_back(Q);
+                }
+}
 
 hipError_t launch_green_lp(const mcmp2_ctx *c, int n_tau, bool grad) {
     switch (c->precision) {

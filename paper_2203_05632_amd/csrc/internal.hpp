@@ -57,11 +57,14 @@ struct mcmp2_ctx {
     int *tiles = nullptr;     // [n_tp][2] (P, Q), P <= Q
     int *work = nullptr;      // [n_slots / 4] tile-pair index per block (-1: idle), XCD-aware order
     int n_slots = 0;          // partial-sum slots: 4 per block (one per wave)
-    double *partial = nullptr;  // [n_tau_max][n_slots][2] per wave slot (direct, exchange)
+    int T16 = 0, n_tp16 = 0;  // BF16 / FP16: 16-walker tiles per side, tile pairs P <= Q
+    int *tiles16 = nullptr;   // [n_tp16][2] (P, Q) in 4 x 8 patches
+    double *partial = nullptr;  // [n_tau_max][max(n_slots, 8 n_tp16)][2] per wave slot (direct, exchange)
     // gradient work space (allocated when want_grad)
     double *Hm = nullptr;       // [n_tau_max][R][R] complex adjoint of G-
     double *Hp = nullptr;       // [n_tau_max][R][R] complex adjoint of G+
     double *psibar = nullptr;   // [nsp][R] complex gradient of psi
+    uint32_t *Vt = nullptr;     // BF16 / FP16 modes: [n_tau_max][nsp][R] psi s_t as packed BF16 pairs
     double *eps_part = nullptr; // [R / 32][nsp] per row tile
 
     Profiler prof;
@@ -98,6 +101,12 @@ hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const dou
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c);
 hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad);
 hipError_t launch_green_lp(const mcmp2_ctx *c, int n_tau, bool grad);
+// BF16 / FP16: 128 x 128 block tiles (16 walkers a side) when they fill the GPU
+bool green_big_selected(const mcmp2_ctx *c, int n_tau);
+void build_big_tiles(int T16, std::vector<int> &tiles);
 hipError_t launch_accumulate(const mcmp2_ctx *c, const double *src, double *sum, double *comp, int64_t n);
-hipError_t launch_grad(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps, double *grad_coeffs);
+hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps);
+hipError_t launch_coef_grad(const mcmp2_ctx *c, double *grad_coeffs);
+hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau);
+int adjoint_lp_row_tiles(const mcmp2_ctx *c);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);

@@ -33,7 +33,10 @@ def _ctx(inp, **kw):
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("name,over,taus", [("C0", dict(n_tau=2), [0.3, 1.4]),
                                              ("C0", dict(m=13, n_occ=6, n_vir=10, n_tau=3), [0.1, 0.6, 3.0]),
-                                             ("C1", dict(), [0.2, 0.9])])
+                                             ("C1", dict(), [0.2, 0.9]),
+                                             # 273 (tau, 16-walker tile pair) items: the BF16 / FP16 modes take
+                                             # the 128x128-tile kernel; m = 200 leaves a half-filled last tile
+                                             ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0])])
 def test_low_precision_step_near_oracle(prec, name, over, taus):
     inp = make_inputs(name, **over)
     wk = initial_walkers(inp)
@@ -86,15 +89,20 @@ def test_systematic_error_below_one_percent_of_sigma(chain_runs, prec):
     assert abs(mean_d) < 0.01 * sbar
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_low_precision_gradients_near_fp64(prec):
-    inp = make_inputs("C1")
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("name,over,taus", [("C1", dict(), [0.3, 1.0]),
+                                             ("C0", dict(m=13, n_occ=6, n_vir=10, n_tau=3), [0.2, 0.7, 2.5]),
+                                             ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0])])
+def test_low_precision_gradients_near_fp64(prec, name, over, taus):
+    """FP32 mode keeps an FP64 adjoint GEMM; BF16 and FP16 modes run the
+    adjoint GEMM on BF16 operands (adjoint blocks and psi S_t)."""
+    inp = make_inputs(name, **over)
     wk = dev(initial_walkers(inp))
-    taus = dev([0.3, 1.0])
+    taus = dev(taus)
     out = {}
     for p in ("fp64", prec):
         ctx = _ctx(inp, precision=p, want_grad=True)
-        e2 = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+        e2 = torch.zeros((inp.n_tau, 3), dtype=torch.float64, device="cuda")
         ge = torch.zeros(inp.n_sp, dtype=torch.float64, device="cuda")
         gc = torch.zeros((2, inp.n_b, inp.n_sp), dtype=torch.complex128, device="cuda")
         ctx.step(wk, taus, e2, grad_eps=ge, grad_coeffs=gc)
@@ -102,5 +110,5 @@ def test_low_precision_gradients_near_fp64(prec):
         out[p] = (ge.cpu().numpy(), gc.cpu().numpy())
     for a, b in zip(out[prec], out["fp64"]):
         err = np.max(np.abs(a - b)) / np.max(np.abs(b))
-        print(f"{prec} gradient max-norm relative deviation {err:.3e}", flush=True)
+        print(f"{prec} {name} {over}: gradient max-norm relative deviation {err:.3e}", flush=True)
         assert err < (1e-5 if prec == "fp32" else 0.01)
