@@ -57,21 +57,21 @@ def kernel_flops(inp) -> dict:
         "spinor_gemm": 16.0 * m * nsp * nb,          # 2m points x 4 components x nsp, real x complex over n_L or n_S
         "green_contract": green_flops(m, nsp, nt),
         "grad": 512.0 * m * (m - 1) * nsp * nt,      # Psibar = sum_t H_t Psi S_t, off-diagonal walker blocks
-        "coef_grad": 32.0 * m * nsp * nb,            # Cbar = X^T Psibar (both spins, re and im)
+        "coef_grad": 16.0 * m * nsp * nb,            # Cbar = X^T Psibar: same shape as the spinor GEMM
     }
 
 
 def operand_type(prec: str, kernel: str) -> str:
-    """MFMA operand type of a kernel in a precision mode: the spinor GEMM runs
-    FP32 MFMAs in every low-precision mode; the adjoint GEMM runs BF16 in the
-    BF16 and FP16 modes and FP64 in FP32 mode; the coefficient gradient is FP64."""
-    if prec == "fp64" or kernel == "coef_grad":
+    """MFMA operand type of a kernel in a precision mode.  BF16 / FP16 modes:
+    spinor GEMM on split BF16 operands (hi + lo, three BF16 products: its
+    algorithmic flops are priced at the BF16 peak), adjoint GEMM and
+    coefficient gradient on BF16, Green's GEMMs on the mode's type.  FP32 mode:
+    FP32 spinor and Green's GEMMs, FP64 adjoint and coefficient gradient."""
+    if prec == "fp64":
         return "fp64"
-    if kernel == "spinor_gemm":
-        return "fp32"
-    if kernel == "grad":
-        return "fp64" if prec == "fp32" else "bf16"
-    return prec
+    if prec == "fp32":
+        return "fp64" if kernel in ("grad", "coef_grad") else "fp32"
+    return prec if kernel == "green_contract" else "bf16"
 
 
 def kernel_table(prof: dict, kflops: dict, K: int, prec: str) -> dict:

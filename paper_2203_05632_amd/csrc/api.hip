@@ -39,7 +39,8 @@ void free_ctx(mcmp2_ctx *c) {
     profiler_release(c->prof);
     void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->psi,
                     c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT,
-                    c->Hm, c->Hp, c->psibar, c->eps_part, c->U, c->Vt, c->tiles16};
+                    c->Hm, c->Hp, c->psibar, c->eps_part, c->U, c->Vt, c->tiles16,
+                    c->Cb, c->Xb, c->XTb, c->PBb};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete c;
@@ -234,6 +235,25 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
         c->U = u;
         TRY(check_hip(hipMemset(c->U, 0, ub), "hipMemset"));  // K padding stays zero
     }
+    if (precision == MCMP2_BF16 || precision == MCMP2_FP16) {
+        auto r64 = [](int v) { return (v + 63) / 64 * 64; };
+        c->nLp = r64(c->nL);
+        c->nbp = c->nLp + r64(c->nS);
+        c->Ep = r64(c->E);
+        auto zalloc = [&](void **p, size_t bytes) {
+            unsigned char *b = nullptr;
+            int rc = dalloc(&b, bytes);
+            *p = b;
+            if (rc == MCMP2_OK) rc = check_hip(hipMemset(b, 0, bytes), "hipMemset");
+            return rc;
+        };
+        TRY(zalloc(&c->Cb, 2 * (size_t)4 * nsp * 3 * c->nbp));  // BF16, split rows of 3 nbp
+        TRY(zalloc(&c->Xb, 2 * (size_t)c->E * 3 * c->nbp));
+        if (want_grad) {
+            TRY(zalloc(&c->XTb, 2 * (size_t)nb * c->Ep));
+            TRY(zalloc(&c->PBb, 2 * (size_t)2 * 4 * nsp * c->Ep));
+        }
+    }
     TRY(dalloc(&c->scale, (size_t)n_tau_max * nsp));
     TRY(dalloc(&c->wtau, (size_t)n_tau_max));
     std::vector<int> work;
@@ -288,6 +308,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(up(c->pnl, nl.data(), nl.size() * sizeof(double)));
     TRY(up(c->coef, coeffs, 2 * 2 * sizeof(double) * (size_t)nb * nsp));
     TRY(up(c->eps, eps, sizeof(double) * nsp));
+    if (c->Cb) TRY(check_hip(launch_coef_lp(c), "coef_lp"));
     TRY(up(c->tiles, tiles.data(), tiles.size() * sizeof(int)));
     TRY(up(c->work, work.data(), work.size() * sizeof(int)));
     if (c->n_tp16) TRY(up(c->tiles16, tiles16.data(), tiles16.size() * sizeof(int)));
@@ -344,6 +365,7 @@ extern "C" int mcmp2_set_coefficients(mcmp2_ctx *c, const double *coeffs, const 
         rc = check_hip(hipMemcpyAsync(c->coef, coeffs, 2 * 2 * sizeof(double) * (size_t)c->nb * c->nsp,
                                       hipMemcpyDeviceToDevice, c->stream),
                        "hipMemcpyAsync");
+    if (rc == MCMP2_OK && coeffs && c->Cb) rc = check_hip(launch_coef_lp(c), "coef_lp");
     if (rc == MCMP2_OK && eps)
         rc = check_hip(hipMemcpyAsync(c->eps, eps, sizeof(double) * c->nsp, hipMemcpyDeviceToDevice, c->stream),
                        "hipMemcpyAsync");

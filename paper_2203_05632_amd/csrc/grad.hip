@@ -242,6 +242,7 @@ hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, doub
 }
 
 hipError_t launch_coef_grad(const mcmp2_ctx *c, double *grad_coeffs) {
+    if (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) return launch_coef_grad_lp(c, grad_coeffs);
     const double2 *psibar = reinterpret_cast<const double2 *>(c->psibar);
     {
         const int n_L_tiles = (c->nL + 15) / 16, n_S_tiles = (c->nS + 15) / 16;

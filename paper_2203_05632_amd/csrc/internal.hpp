@@ -65,6 +65,14 @@ struct mcmp2_ctx {
     double *Hp = nullptr;       // [n_tau_max][R][R] complex adjoint of G+
     double *psibar = nullptr;   // [nsp][R] complex gradient of psi
     uint32_t *Vt = nullptr;     // BF16 / FP16 modes: [n_tau_max][nsp][R] psi s_t as packed BF16 pairs
+    // BF16 / FP16 modes: BF16 operands of the spinor GEMM and the coefficient
+    // gradient (primitive sets padded to nLp, nSp = nbp - nLp; points padded
+    // to Ep; all multiples of 64, padding zero)
+    int nLp = 0, nbp = 0, Ep = 0;
+    void *Cb = nullptr;   // [4 nsp][3 nbp]: row 4 k + 2 s + ri = part ri of C[s][mu][k], split [hi|hi|lo] per set
+    void *Xb = nullptr;   // [E][3 nbp] basis values per point, split [hi|lo|hi] per set
+    void *XTb = nullptr;  // [nb][Ep] basis values per primitive (gradients)
+    void *PBb = nullptr;  // [2 sets][4 nsp][Ep] psi gradient (gradients)
     double *eps_part = nullptr; // [R / 32][nsp] per row tile
 
     Profiler prof;
@@ -108,5 +116,8 @@ hipError_t launch_accumulate(const mcmp2_ctx *c, const double *src, double *sum,
 hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps);
 hipError_t launch_coef_grad(const mcmp2_ctx *c, double *grad_coeffs);
 hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau);
+hipError_t launch_coef_lp(const mcmp2_ctx *c);
+hipError_t launch_spinor_lp(const mcmp2_ctx *c);
+hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, double *grad_coeffs);
 int adjoint_lp_row_tiles(const mcmp2_ctx *c);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);

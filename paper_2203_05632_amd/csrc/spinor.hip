@@ -191,6 +191,7 @@ hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const dou
 }
 
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c) {
+    if (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) return launch_spinor_lp(c);
     dim3 grid((c->nsp + 15) / 16, c->E / 16, 2);
     if (c->precision == MCMP2_FP64)
         spinor_gemm_kernel<double><<<grid, 256, 0, c->stream>>>(c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R,

@@ -1,0 +1,283 @@
+// Spinor values (Eq. (C) of the paper) and the coefficient gradient on BF16
+// MFMAs (FP32 accumulation), used by the BF16 and FP16 modes (BF16 for its
+// 8-bit exponent: basis values, coefficients and psi gradients span more than
+// FP16's range).
+//
+// Both are real GEMMs over a K range with both operands stored row-major
+// with K contiguous, so one 128 x 128-tile main loop (lp_gemm_tile) serves:
+//   spinor values  psi[k][4 pt + 2 set + s] = sum_mu C[s][mu][k] chi_mu(r_pt)
+//       A = Cb  [r = 4 k + 2 s + ri][mu'],  B = Xb [pt][mu'],  K = mu' of one set
+//   coefficient gradient  Cbar[s][mu][k] = sum_pt chi_mu(r_pt) Psibar[k][4 pt + 2 set(mu) + s]
+//       A = XTb [mu][pt],  B = PBb [set][r = 4 k + 2 s + ri][pt],  K = pt
+// (ri: real / imaginary part; points padded to Ep, a multiple of 64).
+//
+// The spinor values feed every Green's function of the step and the
+// coefficients are fixed over the run (a rounding of C is a fixed change of
+// the orbitals, i.e. a bias, not noise), so the spinor GEMM runs split BF16:
+// v = hi + lo with hi = bf16(v), lo = bf16(v - hi), and
+//   C X ~ C_hi X_hi + C_hi X_lo + C_lo X_hi
+// (relative error about 2^-16), as one GEMM over a tripled K: per set, rows
+// of Cb hold [hi | hi | lo] and rows of Xb [hi | lo | hi], each block the
+// set's primitives padded to a multiple of 64 (nLp, nSp; nbp = nLp + nSp, row
+// length 3 nbp).  Padding entries are zero for the context's life.
+#include <algorithm>
+
+#include "internal.hpp"
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int LKW = 32;        // 32-bit words (two K values each) per row per chunk: 64 K values
+constexpr int LROW = LKW + 4;  // padded LDS row in words (144 B)
+constexpr int LBM = 128;       // block tile rows and columns
+
+template <typename T>
+__device__ inline f4v mfma_lp(u32x4 a, u32x4 b, f4v c) {
+    if constexpr (__is_same(T, __bf16))
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                       0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                      0, 0);
+}
+
+// One 128 x 128 tile of D = A B^T over K in [0, K) (K a multiple of 64):
+// A rows a_row0 .., B rows b_row0 .. (row-major, K contiguous, leading
+// dimensions lda / ldb in elements of T; rows at or past a_rows / b_rows read
+// the last valid row).  256 threads; wave (wr, wc) = (wave >> 1, wave & 1)
+// owns rows 64 wr .. and columns 64 wc ..; acc[i][j] element v is D[64 wr +
+// 16 i + 4 (l / 16) + v][64 wc + 16 j + l % 16].
+template <typename T>
+__device__ __attribute__((always_inline)) inline void lp_gemm_tile(const T *__restrict__ A, int lda, int a_row0,
+                                                                   int a_rows, const T *__restrict__ B, int ldb,
+                                                                   int b_row0, int b_rows, int K, uint32_t *lds,
+                                                                   f4v (&acc)[4][4]) {
+    constexpr int STAGE = 2 * LBM * LROW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+    // staging unit u = tid + 256 j (j < 8): stage row u / 8 (A rows, then B rows), words 4 (u % 8) ..
+    const uint32_t *src[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int u = tid + 256 * j, row = u >> 3;
+        const T *p = row < LBM ? A + (size_t)min(a_row0 + row, a_rows - 1) * lda
+                               : B + (size_t)min(b_row0 + row - LBM, b_rows - 1) * ldb;
+        src[j] = reinterpret_cast<const uint32_t *>(p) + 4 * (u & 7);
+    }
+    u32x4 rg[8];
+    auto gload = [&](int w0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rg[j] = *reinterpret_cast<const u32x4 *>(src[j] + w0);
+    };
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int u = tid + 256 * j;
+            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + (u >> 3) * LROW + 4 * (u & 7)]) = rg[j];
+        }
+    };
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int n = K / (2 * LKW);
+    if (n == 0) return;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < n) gload((c + 1) * LKW);
+        const uint32_t *la = &lds[buf * STAGE + (64 * wr + li) * LROW + 4 * lk];
+        const uint32_t *lb = &lds[buf * STAGE + (LBM + 64 * wc + li) * LROW + 4 * lk];
+#pragma unroll
+        for (int ks = 0; ks < LKW; ks += 16) {
+            u32x4 a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(la + 16 * i * LROW + ks);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const u32x4 *>(lb + 16 * j * LROW + ks);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_lp<T>(a[i], b[j], acc[i][j]);
+        }
+        if (c + 1 < n) lstore(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+__device__ inline void split_bf16(double v, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)(float)v;
+    lo = (__bf16)(float)(v - (double)(float)hi);
+}
+
+// offset of primitive mu's first block in a split row (set L, then set S)
+__device__ inline int split_base(int mu, int nL, int nLp) { return mu < nL ? mu : 3 * nLp + (mu - nL); }
+
+// Cb[4 k + 2 s + ri][.] = part ri of C[s][mu][k] split as [hi | hi | lo]; grid (ceil(nb / 64), nsp)
+__global__ __launch_bounds__(256) void coef_lp_kernel(const double2 *__restrict__ coef, int nb, int nL, int nLp,
+                                                      int nSp, int nsp, __bf16 *__restrict__ Cb) {
+    const int k = blockIdx.y;
+    const int mu = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;  // q = 2 s + ri
+    if (mu >= nb) return;
+    const double2 cv = coef[((size_t)(q >> 1) * nb + mu) * nsp + k];
+    __bf16 hi, lo;
+    split_bf16((q & 1) ? cv.y : cv.x, hi, lo);
+    const int blk = mu < nL ? nLp : nSp;
+    __bf16 *o = Cb + ((size_t)4 * k + q) * 3 * (nLp + nSp) + split_base(mu, nL, nLp);
+    o[0] = hi;
+    o[blk] = hi;
+    o[2 * blk] = lo;
+}
+
+// XT (FP64 [nb][E]) -> Xb [pt][.] split as [hi | lo | hi] and, for
+// gradients, XTb [mu][pt] (row length Ep).  64 x 64 tiles through LDS;
+// grid (ceil(nb / 64), ceil(E / 64)).
+__global__ __launch_bounds__(256) void x_lp_kernel(const double *__restrict__ XT, int nb, int nL, int nLp, int nSp,
+                                                   int E, int Ep, __bf16 *__restrict__ Xb, __bf16 *__restrict__ XTb) {
+    __shared__ double tile[64][65];
+    const int mu0 = blockIdx.x * 64, pt0 = blockIdx.y * 64, tid = threadIdx.x;
+    const int ldx = 3 * (nLp + nSp);
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int r = e >> 6, p = e & 63, mu = mu0 + r, pt = pt0 + p;
+        const double v = (mu < nb && pt < E) ? XT[(size_t)mu * E + pt] : 0.0;
+        tile[r][p] = v;
+        if (XTb && mu < nb && pt < E) XTb[(size_t)mu * Ep + pt] = (__bf16)(float)v;
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int p = e >> 6, r = e & 63, mu = mu0 + r, pt = pt0 + p;
+        if (mu < nb && pt < E) {
+            __bf16 hi, lo;
+            split_bf16(tile[r][p], hi, lo);
+            const int blk = mu < nL ? nLp : nSp;
+            __bf16 *o = Xb + (size_t)pt * ldx + split_base(mu, nL, nLp);
+            o[0] = hi;
+            o[blk] = lo;
+            o[2 * blk] = hi;
+        }
+    }
+}
+
+// psibar (double2 [nsp][R], R index 4 pt + 2 set + s) -> PBb[set][4 k + 2 s + ri][pt]
+__global__ __launch_bounds__(256) void psibar_lp_kernel(const double2 *__restrict__ psibar, int nsp, int R, int E,
+                                                        int Ep, __bf16 *__restrict__ PBb) {
+    const int pt = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
+    if (pt >= E) return;
+    const size_t plane = (size_t)4 * nsp * Ep;
+    for (int c = 0; c < 4; ++c) {
+        const double2 v = psibar[(size_t)k * R + 4 * pt + c];
+        const int set = c >> 1, s = c & 1;
+        __bf16 *o = PBb + set * plane + (size_t)(4 * k + 2 * s) * Ep + pt;
+        o[0] = (__bf16)(float)v.x;
+        o[Ep] = (__bf16)(float)v.y;
+    }
+}
+
+// Work items (set, row tile, column tile) dealt to the XCDs in contiguous
+// ranges (block b runs on XCD b % 8).
+__device__ inline int xcd_item(int n_items) {
+    const int per = (n_items + 7) / 8;
+    return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
+// psi[k][4 pt + 2 set + s] (float2): rows r = 4 k + 2 s + ri of Cb, columns pt
+__global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict__ Cb, const __bf16 *__restrict__ Xb,
+                                                        int nsp, int nLp, int nSp, int E, int R, int n_rt, int n_ct,
+                                                        float2 *__restrict__ psi) {
+    __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LROW];
+    const int n_items = 2 * n_rt * n_ct;
+    const int item = xcd_item(n_items);
+    if (item >= n_items) return;
+    const int set = item / (n_rt * n_ct), rest = item % (n_rt * n_ct), rt = rest / n_ct, ct = rest % n_ct;
+    const int koff = set ? 3 * nLp : 0, K = 3 * (set ? nSp : nLp), ld = 3 * (nLp + nSp);
+    f4v acc[4][4];
+    lp_gemm_tile<__bf16>(Cb + koff, ld, LBM * rt, 4 * nsp, Xb + koff, ld, LBM * ct, E, K, lds, acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = (LBM * rt + 64 * wr + 16 * i) / 4 + lk;  // rows 4 k + v, v = 2 s + ri
+        if (k >= nsp) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pt = LBM * ct + 64 * wc + 16 * j + li;
+            if (pt >= E) continue;
+            float2 *o = psi + (size_t)k * R + 4 * pt + 2 * set;
+            o[0] = float2{acc[i][j][0], acc[i][j][1]};  // alpha
+            o[1] = float2{acc[i][j][2], acc[i][j][3]};  // beta
+        }
+    }
+}
+
+// grad_coeffs[s][mu][k] (double2): rows mu of one set (XTb), columns r = 4 k + 2 s + ri (PBb[set])
+__global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restrict__ XTb, const __bf16 *__restrict__ PBb,
+                                                           int nb, int nL, int nsp, int Ep, int n_rt_L, int n_rt_S,
+                                                           int n_ct, double *__restrict__ grad_coeffs) {
+    __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LROW];
+    const int n_items = (n_rt_L + n_rt_S) * n_ct;
+    const int item = xcd_item(n_items);
+    if (item >= n_items) return;
+    const int rt_all = item / n_ct, ct = item % n_ct;
+    const int set = rt_all >= n_rt_L;
+    const int mu_lo = set ? nL : 0, mu_hi = set ? nb : nL;
+    const int mu0 = mu_lo + LBM * (set ? rt_all - n_rt_L : rt_all);
+    f4v acc[4][4];
+    lp_gemm_tile<__bf16>(XTb, Ep, mu0, mu_hi, PBb + (size_t)set * 4 * nsp * Ep, Ep, LBM * ct, 4 * nsp, Ep, lds, acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = LBM * ct + 64 * wc + 16 * j + li;
+        const int k = r >> 2, s = (r >> 1) & 1, ri = r & 1;
+        if (k >= nsp) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int mu = mu0 + 64 * wr + 16 * i + 4 * lk + v;
+                if (mu < mu_hi) grad_coeffs[(((size_t)s * nb + mu) * nsp + k) * 2 + ri] = acc[i][j][v];
+            }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_coef_lp(const mcmp2_ctx *c) {
+    dim3 g((c->nb + 63) / 64, c->nsp);
+    coef_lp_kernel<<<g, 256, 0, c->stream>>>(reinterpret_cast<const double2 *>(c->coef), c->nb, c->nL, c->nLp,
+                                             c->nbp - c->nLp, c->nsp, reinterpret_cast<__bf16 *>(c->Cb));
+    return hipGetLastError();
+}
+
+hipError_t launch_spinor_lp(const mcmp2_ctx *c) {
+    dim3 g((c->nb + 63) / 64, (c->E + 63) / 64);
+    x_lp_kernel<<<g, 256, 0, c->stream>>>(c->XT, c->nb, c->nL, c->nLp, c->nbp - c->nLp, c->E, c->Ep,
+                                          reinterpret_cast<__bf16 *>(c->Xb), reinterpret_cast<__bf16 *>(c->XTb));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n_rt = (4 * c->nsp + LBM - 1) / LBM, n_ct = (c->E + LBM - 1) / LBM;
+    const int n_items = 2 * n_rt * n_ct;
+    spinor_lp_kernel<<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
+        reinterpret_cast<const __bf16 *>(c->Cb), reinterpret_cast<const __bf16 *>(c->Xb), c->nsp, c->nLp,
+        c->nbp - c->nLp, c->E, c->R, n_rt, n_ct, reinterpret_cast<float2 *>(c->psi));
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, double *grad_coeffs) {
+    dim3 g1((c->E + 255) / 256, c->nsp);
+    psibar_lp_kernel<<<g1, 256, 0, c->stream>>>(reinterpret_cast<const double2 *>(c->psibar), c->nsp, c->R, c->E,
+                                                c->Ep, reinterpret_cast<__bf16 *>(c->PBb));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n_rt_L = (c->nL + LBM - 1) / LBM, n_rt_S = (c->nS + LBM - 1) / LBM;
+    const int n_ct = (4 * c->nsp + LBM - 1) / LBM;
+    const int n_items = (n_rt_L + n_rt_S) * n_ct;
+    coef_grad_lp_kernel<<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
+        reinterpret_cast<const __bf16 *>(c->XTb), reinterpret_cast<const __bf16 *>(c->PBb), c->nb, c->nL, c->nsp,
+        c->Ep, n_rt_L, n_rt_S, n_ct, grad_coeffs);
+    return hipGetLastError();
+}

@@ -3,8 +3,11 @@ accumulation; scalings, weights, contractions and sums in FP64).
 
 * Per step at fixed walkers and tau: deviation from the FP64 oracle, measured
   on the scale of the pair terms (mean |pair term|), within a bound set by the
-  operand precision (unit roundoff 2^-24, 2^-8, 2^-11 times a safety factor
-  for the K-sums and the quartic contraction).
+  operand precision.  In the BF16 / FP16 modes every spinor value carries three
+  roundings to the operand type (basis value, coefficient, scaled operand of
+  the Green's-function GEMM), and a pair term is of degree 8 in the spinor
+  values: bound 8 u for unit roundoff u = 2^-8 (BF16), 2^-11 (FP16).  FP32
+  mode rounds only the GEMM operands to FP32: bound 1e-6 (about 17 u).
 * Over a chain: the systematic error -- mean over steps of the paired
   difference low - FP64 on the same walker trajectory (valid because the
   walker weights do not depend on the operand precision) -- must stay below
@@ -22,7 +25,7 @@ from oracle.weights import n_g, tau_lambda
 from synth import initial_walkers, make_inputs
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
-BOUND = {"fp32": 1e-6, "bf16": 0.02, "fp16": 1e-3}
+BOUND = {"fp32": 1e-6, "bf16": 8 * 2.0 ** -8, "fp16": 8 * 2.0 ** -11}
 
 
 def _ctx(inp, **kw):
