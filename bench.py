@@ -8,9 +8,12 @@ all on the GPU through libmcmp2; with gradients, also the adjoint (eps and
 coefficient gradients) and their compensated accumulation over steps.
 Inputs are synthetic and seeded (synth/).
 
-Prints one JSON line.  The headline `value` is MC steps/s of the FP64 path
-on the chosen workload (default: the 340-spinor, 128-walker-pair FP64
-baseline workload).  Every variant (FP32 / BF16 / FP16 operands, with and
+Prints one JSON line (progress goes to stderr).  The headline `value` is MC
+steps/s of the FP64 path on the chosen workload (default: the 340-spinor,
+128-walker-pair FP64 baseline workload).  `largest` repeats the FP64, FP64 +
+gradient and BF16 / FP16 (+ gradient) runs on the largest workload (1620
+spinors, 512 walker pairs, 4 tau per step), where the mixed-precision path
+with gradients is compared with the FP64 path with gradients.  Every variant (FP32 / BF16 / FP16 operands, with and
 without gradients) replays the same burned-in walker trajectory, so its
 per-step values pair with the FP64 ones: `systematic_over_sigma` is
 |mean(low - FP64)| / sigma_bar(FP64) (blocking, N_b = 100).  `roofline`
@@ -28,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad"]
+HEADLINE_VARIANTS = [("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True),
+                     ("fp16", True)]
+LARGEST_VARIANTS = [("fp64", True), ("bf16", False), ("bf16", True), ("fp16", True)]
 METRIC = "MC steps/s and var×time for E2(+grad), FP32/BF16 vs FP64, 1 MI355X"
 # published dense peaks of one MI355X (TFLOP/s) for the GEMM operand type
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
@@ -41,6 +47,38 @@ WORKLOADS = {
     "C4": "largest: 6 nuclei (octahedron), 1000 L / 2300 S primitives, 120 occupied / 1500 virtual spinors, "
           "m=512 walker pairs, 4 tau per step",
 }
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "green_contract_C1_fp64_traffic.md")
+
+
+def sources_sha256(files) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(config: str):
+    """HBM bytes per launch of the Green's-function kernel from the committed
+    rocprofv3 counter record (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a copy of known size), or None when no record matches this
+    workload or the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            text = fh.read()
+        rec = json.loads(text.split("```json")[1].split("```")[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("workload") != config or rec.get("sources_sha256") != sources_sha256(rec.get("sources", [])):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def green_flops(m: int, n_sp: int, n_tau: int) -> float:
@@ -166,31 +204,77 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=None, help="timed steps per variant (default: --steps)")
     ap.add_argument("--no-variants", action="store_true", help="FP64 headline only")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0: skip)")
+    ap.add_argument("--no-largest", action="store_true", help="skip the largest-workload (C4) section")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a known-size kernel for counter calibration)")
+    ap.add_argument("--largest-steps", type=int, default=1000, help="timed C4 steps per variant")
+    ap.add_argument("--largest-grad-steps", type=int, default=200, help="timed C4 steps of the FP64 gradient run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one MC chain on one MI355X); --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from oracle.blocking import blocking
-    from paper_2203_05632_amd import Context
-    from synth import initial_walkers, make_inputs
-
     torch.cuda.set_device(0)
-    inp = make_inputs(args.config)
-    key = (0, 0)
-    wk0 = initial_walkers(inp)
-    # burn-in on an FP64 context (walker moves do not depend on the operand precision)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    head = measure_workload(args.config, args.steps, args.warmup, args.burnin,
+                            [] if args.no_variants else HEADLINE_VARIANTS, args.variant_steps)
+    K, inp, elapsed, sbar = args.steps, head["inp"], head["elapsed"], head["sbar"]
+    largest = None
+    if not args.no_largest and args.config != "C4":
+        lw = measure_workload("C4", args.largest_steps, 5, 50, LARGEST_VARIANTS, None,
+                              grad_steps=args.largest_grad_steps)
+        largest = {"workload": f"C4 {WORKLOADS['C4']}", "fp64": lw["fp64"], "variants": lw["variants"]}
+        g64 = lw["variants"].get("fp64+grad", {}).get("steps_per_s")
+        b16 = lw["variants"].get("bf16+grad", {})
+        if g64 and b16:
+            largest["bf16_grad_over_fp64_grad"] = round(b16["steps_per_s"] / g64, 3)
+            largest["bf16_grad_over_fp64"] = round(b16["steps_per_s"] / lw["fp64"]["steps_per_s"], 3)
+            largest["bf16_grad_green_mfma_frac"] = b16["kernels"]["green_contract"]["peak_frac"]
+            largest["bf16_grad_systematic_over_sigma"] = b16.get("systematic_over_sigma")
+
+    cpu = cpu_baseline(inp, head["wk0"], head["key"], head["delta"], args.cpu_seconds) if args.cpu_seconds > 0 \
+        else None
+    out = {
+        "metric": METRIC, "value": round(K / elapsed, 2), "unit": "MC steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / K, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config} {WORKLOADS[args.config]}", "m": inp.m, "n_tau": inp.n_tau,
+                   "n_L": inp.n_L, "n_S": inp.n_S, "n_occ": inp.n_occ, "n_vir": inp.n_vir,
+                   "precision": "fp64", "grad": False},
+        "var_x_time": None if sbar is None else float(f"{sbar ** 2 * elapsed:.6g}"),
+        "var_x_time_unit": "Eh^2 s",
+        "e2_mean": float(f"{head['ref_vals'].mean():.6g}"),
+        "sigma_bar": None if sbar is None else float(f"{sbar:.6g}"),
+        "roofline": head["roofline"],
+        "kernels": head["fp64"]["kernels"],
+        "variants": head["variants"],
+        "largest": largest,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def burn_in(inp, wk0, key, n_burn):
+    """Metropolis burn-in on an FP64 context (walker moves do not depend on
+    the operand precision), adapting delta toward acceptance 0.5."""
+    import torch
+
+    from paper_2203_05632_amd import Context
     drv = Context.from_inputs(inp)
     wk = torch.as_tensor(wk0, device="cuda")
     w = torch.zeros(inp.m, dtype=torch.float64, device="cuda")
     n_acc = torch.zeros(1, dtype=torch.int32, device="cuda")
     drv.pair_weights(wk, w)
     delta, step = 0.5, 0
-    for _ in range(args.burnin // 10):
+    for _ in range(n_burn // 10):
         n_acc.zero_()
         for _ in range(10):
             drv.metropolis(wk, w, key, step, delta, n_acc)
@@ -198,11 +282,23 @@ def main():
         delta *= 1.1 if n_acc.item() / (10.0 * inp.m) > 0.5 else 0.9
     torch.cuda.synchronize()
     drv.close()
-    state = {"wk": wk, "w": w, "key": key, "delta": delta, "step": step}
+    return {"wk": wk, "w": w, "key": key, "delta": delta, "step": step}
 
-    K, W = args.steps, args.warmup
+
+def measure_workload(name, K, W, n_burn, variants, Kv=None, grad_steps=None):
+    """FP64 reference run plus the listed (precision, grad) variants, all
+    replaying one burned-in trajectory."""
+    from oracle.blocking import blocking
+    from synth import initial_walkers, make_inputs
+
+    inp = make_inputs(name)
+    key = (0, 0)
+    wk0 = initial_walkers(inp)
+    state = burn_in(inp, wk0, key, n_burn)
+    progress(f"{name}: inputs ready, burn-in done")
     elapsed, ref_vals, prof = run_variant(inp, "fp64", False, state, K, W, profile=True)
     steps_per_s = K / elapsed
+    progress(f"{name} fp64: {steps_per_s:.2f} steps/s")
     sbar = blocking(ref_vals, 100)[1] if K >= 200 else None
     flops = green_flops(inp.m, inp.n_sp, inp.n_tau)
     kflops = kernel_flops(inp)
@@ -212,47 +308,32 @@ def main():
         avg_s = tot_ms / K / 1e3                      # per step (one launch per group of <= 4 tau)
         ach = flops / avg_s / 1e12
         roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-                    "frac": round(ach / PEAK_TFLOPS["fp64"], 4), "traffic": None, "kernel": "green_contract",
+                    "frac": round(ach / PEAK_TFLOPS["fp64"], 4), "traffic": recorded_traffic(name),
+                    "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                    "kernel": "green_contract",
                     "avg_us": round(tot_ms / n_l * 1e3, 2), "launches_per_step": n_l // K,
                     "flops_per_launch": flops / (n_l // K)}
-
-    variants = {}
-    if not args.no_variants:
-        Kv = args.variant_steps or K
-        for prec, grad in (("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True),
-                           ("fp16", True)):
-            el, vals, vprof = run_variant(inp, prec, grad, state, Kv, W, profile=True)
-            name = prec + ("+grad" if grad else "")
-            v = {"steps_per_s": round(Kv / el, 2), "ms_per_step": round(1e3 * el / Kv, 5),
-                 "speedup_vs_fp64": round((Kv / el) / steps_per_s, 3)}
-            if grad and "fp64+grad" in variants:
-                v["speedup_vs_fp64_grad"] = round((Kv / el) / variants["fp64+grad"]["steps_per_s"], 3)
-            kern = kernel_table(vprof, kflops, Kv, prec)
-            v["kernels"] = kern
-            if Kv == K and Kv >= 200:
-                d = vals - ref_vals
-                v["systematic_over_sigma"] = float(f"{abs(d.mean()) / sbar:.3e}")
-                v["var_x_time"] = float(f"{blocking(vals, 100)[1] ** 2 * el:.6g}")
-            variants[name] = v
-
-    cpu = cpu_baseline(inp, wk0, key, delta, args.cpu_seconds) if args.cpu_seconds > 0 else None
-    out = {
-        "metric": METRIC, "value": round(steps_per_s, 2), "unit": "MC steps/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": round(1e3 * elapsed / K, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.config} {WORKLOADS[args.config]}", "m": inp.m, "n_tau": inp.n_tau,
-                   "n_L": inp.n_L, "n_S": inp.n_S, "n_occ": inp.n_occ, "n_vir": inp.n_vir,
-                   "precision": "fp64", "grad": False},
-        "var_x_time": None if sbar is None else float(f"{sbar ** 2 * elapsed:.6g}"),
-        "var_x_time_unit": "Eh^2 s",
-        "e2_mean": float(f"{ref_vals.mean():.6g}"),
-        "sigma_bar": None if sbar is None else float(f"{sbar:.6g}"),
-        "roofline": roofline,
-        "kernels": kernel_table(prof, kflops, K, "fp64"),
-        "variants": variants,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    out_vars = {}
+    for prec, grad in variants:
+        Kn = (grad_steps if (grad and prec == "fp64" and grad_steps) else (Kv or K))
+        el, vals, vprof = run_variant(inp, prec, grad, state, Kn, W, profile=True)
+        vname = prec + ("+grad" if grad else "")
+        v = {"steps": Kn, "steps_per_s": round(Kn / el, 2), "ms_per_step": round(1e3 * el / Kn, 5),
+             "speedup_vs_fp64": round((Kn / el) / steps_per_s, 3)}
+        if grad and "fp64+grad" in out_vars:
+            v["speedup_vs_fp64_grad"] = round((Kn / el) / out_vars["fp64+grad"]["steps_per_s"], 3)
+        v["kernels"] = kernel_table(vprof, kflops, Kn, prec)
+        if Kn == K and Kn >= 200:
+            d = vals - ref_vals
+            v["systematic_over_sigma"] = float(f"{abs(d.mean()) / sbar:.3e}")
+            v["var_x_time"] = float(f"{blocking(vals, 100)[1] ** 2 * el:.6g}")
+        out_vars[vname] = v
+        progress(f"{name} {vname}: {v['steps_per_s']} steps/s")
+    return {"inp": inp, "wk0": wk0, "key": key, "delta": state["delta"], "elapsed": elapsed, "ref_vals": ref_vals,
+            "sbar": sbar, "roofline": roofline,
+            "fp64": {"steps": K, "steps_per_s": round(steps_per_s, 2), "ms_per_step": round(1e3 * elapsed / K, 5),
+                     "kernels": kernel_table(prof, kflops, K, "fp64")},
+            "variants": out_vars}
 
 
 if __name__ == "__main__":
