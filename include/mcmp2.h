@@ -72,14 +72,23 @@ typedef struct {
  *   eps        : host, [n_occ+n_vir] spinor energies, occupied first.
  *   m_pairs    : number of electron-pair walkers m (>= 2), Eq. redundant.
  *   n_tau_max  : largest n_tau a step will be given (>= 1).
- *   precision  : MCMP2_FP64: every GEMM in FP64.  MCMP2_FP32 / _BF16 / _FP16:
- *                the spinor GEMM on FP32 MFMA and the Green's-function GEMMs on
- *                FP32 / BF16 / FP16 MFMA operands, all with FP32 accumulation;
- *                exp(+-eps tau) scalings (applied as square roots to both
- *                operands), weights, contractions, adjoint GEMMs and all sums
- *                stay in FP64.
+ *   precision  : MFMA operand types of the step's GEMMs, all with FP32
+ *                accumulation outside FP64 mode:
+ *                  mode   spinor GEMM     Green's GEMMs  adjoint GEMM  coefficient gradient
+ *                  FP64   FP64            FP64           FP64          FP64
+ *                  FP32   FP32            FP32           FP64          FP64
+ *                  BF16   split BF16 (*)  BF16           BF16          BF16
+ *                  FP16   split BF16 (*)  FP16           BF16          BF16
+ *                (*) basis values and coefficients split as hi + lo BF16
+ *                parts, three products (about 16 significant bits).  The
+ *                adjoint GEMM and coefficient gradient of FP16 mode use BF16
+ *                for its exponent range.  exp(+-eps tau) scalings (applied as
+ *                square roots to both Green's-function operands, rounded
+ *                once), pair weights, the pair contraction and every sum stay
+ *                in FP64.
  *   want_grad  : non-zero to allow gradient outputs in mcmp2_step; allocates
- *                2 n_tau_max (8 m_pad)^2 complex adjoint matrices (m_pad = m
+ *                2 n_tau_max (8 m_pad)^2 complex adjoint matrices (FP64, or
+ *                packed BF16 pairs in the BF16 / FP16 modes; m_pad = m
  *                rounded up to a multiple of 8).
  *   hip_stream : hipStream_t to enqueue on (NULL = default stream).
  *   out        : receives the context.

@@ -3,11 +3,11 @@ accumulation; scalings, weights, contractions and sums in FP64).
 
 * Per step at fixed walkers and tau: deviation from the FP64 oracle, measured
   on the scale of the pair terms (mean |pair term|), within a bound set by the
-  operand precision.  In the BF16 / FP16 modes every spinor value carries three
-  roundings to the operand type (basis value, coefficient, scaled operand of
-  the Green's-function GEMM), and a pair term is of degree 8 in the spinor
-  values: bound 8 u for unit roundoff u = 2^-8 (BF16), 2^-11 (FP16).  FP32
-  mode rounds only the GEMM operands to FP32: bound 1e-6 (about 17 u).
+  operand precision.  In the BF16 / FP16 modes every Green's-function operand
+  (spinor value times sqrt(exp(+-eps tau))) is rounded once to the operand
+  type (the split-BF16 spinor GEMM adds about 2^-16), and a pair term has
+  degree 8 in the spinor values: bound 8 u for unit roundoff u = 2^-8 (BF16),
+  2^-11 (FP16).  FP32 mode: bound 1e-6 (about 17 u).
 * Over a chain: the systematic error -- mean over steps of the paired
   difference low - FP64 on the same walker trajectory (valid because the
   walker weights do not depend on the operand precision) -- must stay below
