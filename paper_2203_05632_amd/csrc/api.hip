@@ -165,6 +165,9 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
         delete c;
         return MCMP2_EDEVICE;
     }
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        c->n_cu < 1)
+        c->n_cu = 256;
     c->stream = (hipStream_t)hip_stream;
     c->n_nuc = basis->n_nuc;
     c->nL = basis->n_L;

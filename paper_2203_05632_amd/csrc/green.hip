@@ -186,7 +186,8 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
     }
 }
 
-// grid: n_slots / 4 blocks; tau samples t0 .. t0 + NT - 1.
+// grid: (n_slots / 4, tau chunks); block (x, y) takes work item x and tau
+// samples t0 .. t0 + NT - 1, t0 = y NT.
 // GRAD: also write, per walker pair, the 8x8 blocks of the Hermitian adjoint
 // matrices H- and H+ (gradient of the step value with respect to the entries
 // of G- and G+, folded as Gbar + Gbar^H) into Hm / Hp [n_tau][R][R] complex.
@@ -194,8 +195,9 @@ template <int NT, bool GRAD>
 __global__ __launch_bounds__(256) void green_contract_kernel(
     const double *__restrict__ psi_, const double *__restrict__ scale, const double *__restrict__ wtau,
     const double *__restrict__ hinv, const int *__restrict__ tiles, const int *__restrict__ work, int n_slots, int R,
-    int no, int nsp, int m, int t0, double *__restrict__ partial, double2 *__restrict__ Hm, double2 *__restrict__ Hp,
+    int no, int nsp, int m, double *__restrict__ partial, double2 *__restrict__ Hm, double2 *__restrict__ Hp,
     double cgrad) {
+    const int t0 = (int)blockIdx.y * NT;
     // 2 buffers x (A, B) x KC x 32 complex = 32 KB; reused for the G tiles of the epilogue
     __shared__ double2 panel[2][2][KC][32];
     __shared__ double spanel[2][4 * KC];  // tau scalings of the buffered chunks
@@ -290,35 +292,45 @@ void build_green_work(int T, double tile_bytes, std::vector<int> &work) {
     }
 }
 
+// Tau samples per block: NT divides n_tau (every block of the launch has NT
+// samples), and the launch's makespan is modelled as (blocks per CU, rounded
+// up) x NT.  Larger NT shares each operand panel across more samples, so the
+// largest NT within 5% of the best makespan is taken.
+int green_tau_chunk(int nblocks, int n_tau, int n_cu) {
+    auto cost = [&](int nt) { return (double)((nblocks * (n_tau / nt) + n_cu - 1) / n_cu) * nt; };
+    double best = 1e300;
+    for (int nt = 1; nt <= 4; ++nt)
+        if (n_tau % nt == 0) best = std::min(best, cost(nt));
+    for (int nt = 4; nt >= 1; --nt)
+        if (n_tau % nt == 0 && cost(nt) <= 1.05 * best) return nt;
+    return 1;
+}
+
 hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
     // gradient of the step value (mean over tau of the pair average): c = -1/2 / (mC2 n_tau)
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
     const int nblocks = c->n_slots / 4;  // one work-list entry per block, four partial slots
-    for (int t0 = 0; t0 < n_tau; t0 += 4) {
-        const int nt = std::min(4, n_tau - t0);
-#define LAUNCH(NTV)                                                                                              \
-    if (grad)                                                                                                    \
-        green_contract_kernel<NTV, true><<<nblocks, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,     \
-                                                                         c->tiles, c->work, c->n_slots, c->R,    \
-                                                                         c->no, c->nsp, c->m, t0, c->partial, Hm, \
-                                                                         Hp, cgrad);                             \
-    else                                                                                                         \
-        green_contract_kernel<NTV, false><<<nblocks, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,    \
-                                                                          c->tiles, c->work, c->n_slots, c->R,   \
-                                                                          c->no, c->nsp, c->m, t0, c->partial,   \
-                                                                          nullptr, nullptr, 0.0)
-        switch (nt) {
-            case 1: LAUNCH(1); break;
-            case 2: LAUNCH(2); break;
-            case 3: LAUNCH(3); break;
-            default: LAUNCH(4); break;
-        }
-#undef LAUNCH
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    const int nt = green_tau_chunk(nblocks, n_tau, c->n_cu);
+    const dim3 grid(nblocks, n_tau / nt);
+#define LAUNCH(NTV)                                                                                             \
+    if (grad)                                                                                                   \
+        green_contract_kernel<NTV, true><<<grid, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,       \
+                                                                      c->tiles, c->work, c->n_slots, c->R, c->no, \
+                                                                      c->nsp, c->m, c->partial, Hm, Hp, cgrad);   \
+    else                                                                                                        \
+        green_contract_kernel<NTV, false><<<grid, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,      \
+                                                                       c->tiles, c->work, c->n_slots, c->R,      \
+                                                                       c->no, c->nsp, c->m, c->partial, nullptr, \
+                                                                       nullptr, 0.0)
+    switch (nt) {
+        case 1: LAUNCH(1); break;
+        case 2: LAUNCH(2); break;
+        case 3: LAUNCH(3); break;
+        default: LAUNCH(4); break;
     }
-    return hipSuccess;
+#undef LAUNCH
+    return hipGetLastError();
 }
 
 

@@ -27,6 +27,7 @@ struct Profiler {
 
 struct mcmp2_ctx {
     int device = 0;
+    int n_cu = 256;  // compute units of the device (queried at init)
     hipStream_t stream = nullptr;
     int n_nuc = 0, nL = 0, nS = 0, nb = 0;
     int no = 0, nv = 0, nsp = 0;

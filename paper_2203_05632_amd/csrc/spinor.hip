@@ -69,7 +69,8 @@ __global__ __launch_bounds__(128) void step_prep_kernel(
     }
 }
 
-// One block computes a 16 (spinor k) x 16 (point) tile of one component set
+// Small problems (too few 16-spinor x 64-point tiles to fill the GPU):
+// one block computes a 16 (spinor k) x 16 (point) tile of one component set
 // (blockIdx.z: 0 = L, 1 = S) for both spins, re and im: four 16x16 FP64
 // accumulators.  The 4 waves split the mu range (every 4th group of 4) and
 // wave 0 adds the partial tiles in a fixed order.  All loads are
@@ -178,6 +179,169 @@ __global__ __launch_bounds__(256) void spinor_gemm_kernel(const double *__restri
     }
 }
 
+
+// Spinor values on FP64 / FP32 MFMA (Eq. (C)):
+//   psi[k][4 pt + 2 set + s] = sum_{mu in set} C[s][mu][k] chi_mu(r_pt)
+// One block: KS spinors x PTS points of one primitive set (L or S), both
+// spins, real and imaginary parts.  As a real GEMM D[r][pt] = sum_mu
+// A[r][mu] B[mu][pt]: B = XT, A rows r = (spinor k, q = 2 s + ri).  Inside
+// each 16-row MFMA tile the rows are ordered so that a lane's four result
+// elements are the four q of one spinor: r = 4 q + kk for the FP64 MFMA
+// (element v at row 4 v + l / 16) and r = 4 kk + q for the FP32 MFMA
+// (element v at row 4 (l / 16) + v).  Operand layout of v_mfma_*_16x16x4:
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] (checked on gfx950).
+// K chunks of 16 primitives go through LDS (double-buffered; registers
+// prefetch the next chunk): As[mu][k][s][ri] and Bs[mu][pt], each mu row
+// padded by 128 B so that 16 lanes read 128 contiguous bytes and the four
+// K-groups of a wave fall 128 B apart modulo the 256-byte bank row.
+// Work items (spinor tile, point tile, set) are dealt to the XCDs in
+// contiguous ranges (block b runs on XCD b % 8), so the point tiles sharing a
+// coefficient tile read it through one L2.
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <typename T, int KS, int PTS>
+__global__ __launch_bounds__(256) void spinor_tile_kernel(const double *__restrict__ XT,
+                                                          const double *__restrict__ coef, int E, int nb, int nL,
+                                                          int nsp, int R, int n_kt, int n_pt,
+                                                          void *__restrict__ psi_out) {
+    constexpr int KC = 16;                 // primitives per chunk
+    constexpr int AROW = 4 * KS + 16;      // doubles per mu row of As
+    constexpr int BROW = PTS + 16;         // doubles per mu row of Bs
+    constexpr int WR = KS / 8;             // 16-row MFMA tiles per wave (a wave owns 2 KS rows)
+    constexpr int WP = PTS / 32;           // 16-point MFMA tiles per wave
+    constexpr int NAU = KC * 2 * KS;       // 16-byte A units per chunk: (mu, s, k) complex
+    constexpr int NBU = KC * PTS / 2;      // 16-byte B units per chunk: (mu, two points)
+    constexpr int PA = (NAU + 255) / 256, PB = (NBU + 255) / 256;
+    static_assert(KS % 8 == 0 && PTS % 32 == 0, "tile shape");
+    typedef T acc_t __attribute__((ext_vector_type(4)));
+    __shared__ __align__(16) double As[2][KC * AROW];
+    __shared__ __align__(16) double Bs[2][KC * BROW];
+
+    const int n_items = 2 * n_kt * n_pt;
+    const int per = (n_items + 7) / 8;
+    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= n_items) return;
+    // set fastest: every XCD's range mixes the short (L) and long (S) K loops
+    const int set = item & 1, rest = item >> 1;
+    const int k0 = (rest / n_pt) * KS, pt0 = (rest % n_pt) * PTS;
+    const int mu_lo = set ? nL : 0, mu_hi = set ? nb : nL;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+
+    d2v ra[PA], rb[PB];
+    // Loads are branch-free: indices past the end read the last valid element;
+    // primitives past the set's end are zeroed (they must not contribute).
+    auto gload = [&](int mu0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < PA; ++j) {
+            const int u = min(tid + 256 * j, NAU - 1);
+            const int ml = u / (2 * KS), sp = (u / KS) & 1, k = u % KS;
+            const int mu = mu0 + ml;
+            const d2v v = *reinterpret_cast<const d2v *>(
+                coef + 2 * (((size_t)sp * nb + min(mu, mu_hi - 1)) * nsp + min(k0 + k, nsp - 1)));
+            ra[j] = mu < mu_hi ? v : d2v{0.0, 0.0};
+        }
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            const int u = min(tid + 256 * j, NBU - 1);
+            const int ml = u / (PTS / 2), p2 = u % (PTS / 2);
+            const int mu = mu0 + ml;
+            const d2v v = *reinterpret_cast<const d2v *>(XT + (size_t)min(mu, mu_hi - 1) * E +
+                                                         min(pt0 + 2 * p2, E - 2));
+            rb[j] = mu < mu_hi ? v : d2v{0.0, 0.0};
+        }
+    };
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < PA; ++j) {
+            const int u = min(tid + 256 * j, NAU - 1);
+            const int ml = u / (2 * KS), sp = (u / KS) & 1, k = u % KS;
+            *reinterpret_cast<d2v *>(&As[buf][ml * AROW + 4 * k + 2 * sp]) = ra[j];
+        }
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            const int u = min(tid + 256 * j, NBU - 1);
+            const int ml = u / (PTS / 2), p2 = u % (PTS / 2);
+            *reinterpret_cast<d2v *>(&Bs[buf][ml * BROW + 2 * p2]) = rb[j];
+        }
+    };
+    acc_t acc[WR][WP];
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WP; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    // A row of this lane inside a 16-row tile: (q, kk) per the MFMA's result layout
+    constexpr bool F64 = __is_same(T, double);
+    const int q = F64 ? li >> 2 : li & 3, kk = F64 ? li & 3 : li >> 2;
+    const int a_off = lk * AROW + 4 * (4 * WR * wr + kk) + q;  // + 16 i (next spinor group) + 4 ks AROW
+    const int b_off = lk * BROW + (PTS / 2) * wc + li;        // + 16 j + 4 ks BROW
+
+    const int n_chunks = (mu_hi - mu_lo + KC - 1) / KC;
+    gload(mu_lo);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < n_chunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < n_chunks) gload(mu_lo + KC * (c + 1));
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            T a[WR], bv[WP];
+#pragma unroll
+            for (int i = 0; i < WR; ++i) a[i] = (T)As[buf][a_off + 16 * i + 4 * ks * AROW];
+#pragma unroll
+            for (int j = 0; j < WP; ++j) bv[j] = (T)Bs[buf][b_off + 16 * j + 4 * ks * BROW];
+#pragma unroll
+            for (int i = 0; i < WR; ++i)
+#pragma unroll
+                for (int j = 0; j < WP; ++j) {
+                    if constexpr (F64)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bv[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        if (c + 1 < n_chunks) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // element v of acc[i][j] = part q = v of spinor k0 + 4 (WR wr + i) + lk at point pt0 + (PTS / 2) wc + 16 j + li
+    typedef T pair_t __attribute__((ext_vector_type(2)));
+    pair_t *out = reinterpret_cast<pair_t *>(psi_out);
+#pragma unroll
+    for (int i = 0; i < WR; ++i) {
+        const int k = k0 + 4 * (WR * wr + i) + lk;
+        if (k >= nsp) continue;
+#pragma unroll
+        for (int j = 0; j < WP; ++j) {
+            const int pt = pt0 + (PTS / 2) * wc + 16 * j + li;
+            if (pt >= E) continue;
+            pair_t *o = out + (size_t)k * R + 4 * pt + 2 * set;
+            o[0] = pair_t{acc[i][j][0], acc[i][j][1]};  // alpha
+            o[1] = pair_t{acc[i][j][2], acc[i][j][3]};  // beta
+        }
+    }
+}
+
+template <typename T, int KS, int PTS>
+hipError_t launch_spinor_tile(const mcmp2_ctx *c) {
+    const int n_kt = (c->nsp + KS - 1) / KS, n_pt = (c->E + PTS - 1) / PTS;
+    const int n_items = 2 * n_kt * n_pt;
+    spinor_tile_kernel<T, KS, PTS><<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
+        c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R, n_kt, n_pt, c->psi);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spinor_typed(const mcmp2_ctx *c) {
+    auto items = [&](int ks, int pts) { return 2 * ((c->nsp + ks - 1) / ks) * ((c->E + pts - 1) / pts); };
+    if (items(32, 128) >= c->n_cu) return launch_spinor_tile<T, 32, 128>(c);
+    if (items(16, 64) >= c->n_cu) return launch_spinor_tile<T, 16, 64>(c);
+    // latency-bound sizes: 16 x 16 tiles, K split over the block's waves, no LDS staging
+    dim3 grid((c->nsp + 15) / 16, c->E / 16, 2);
+    spinor_gemm_kernel<T><<<grid, 256, 0, c->stream>>>(c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R, c->psi);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau) {
@@ -192,12 +356,5 @@ hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const dou
 
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c) {
     if (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) return launch_spinor_lp(c);
-    dim3 grid((c->nsp + 15) / 16, c->E / 16, 2);
-    if (c->precision == MCMP2_FP64)
-        spinor_gemm_kernel<double><<<grid, 256, 0, c->stream>>>(c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R,
-                                                                c->psi);
-    else
-        spinor_gemm_kernel<float><<<grid, 256, 0, c->stream>>>(c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R,
-                                                               c->psi);
-    return hipGetLastError();
+    return c->precision == MCMP2_FP64 ? launch_spinor_typed<double>(c) : launch_spinor_typed<float>(c);
 }

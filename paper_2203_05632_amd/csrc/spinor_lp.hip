@@ -177,8 +177,7 @@ __global__ __launch_bounds__(256) void psibar_lp_kernel(const double2 *__restric
     }
 }
 
-// Work items (set, row tile, column tile) dealt to the XCDs in contiguous
-// ranges (block b runs on XCD b % 8).
+// Work items dealt to the XCDs in contiguous ranges (block b runs on XCD b % 8).
 __device__ inline int xcd_item(int n_items) {
     const int per = (n_items + 7) / 8;
     return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -192,7 +191,8 @@ __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict
     const int n_items = 2 * n_rt * n_ct;
     const int item = xcd_item(n_items);
     if (item >= n_items) return;
-    const int set = item / (n_rt * n_ct), rest = item % (n_rt * n_ct), rt = rest / n_ct, ct = rest % n_ct;
+    // set fastest: every XCD's range mixes the short (L) and long (S) K loops
+    const int set = item & 1, rest = item >> 1, rt = rest / n_ct, ct = rest % n_ct;
     const int koff = set ? 3 * nLp : 0, K = 3 * (set ? nSp : nLp), ld = 3 * (nLp + nSp);
     f4v acc[4][4];
     lp_gemm_tile<__bf16>(Cb + koff, ld, LBM * rt, 4 * nsp, Xb + koff, ld, LBM * ct, E, K, lds, acc);
