@@ -18,7 +18,9 @@ without gradients) replays the same burned-in walker trajectory, so its
 per-step values pair with the FP64 ones: `systematic_over_sigma` is
 |mean(low - FP64)| / sigma_bar(FP64) (blocking, N_b = 100).  `roofline`
 places the dominant kernel (Green's-function GEMMs + pair contraction) on the
-FP64 MFMA roofline from HIP-event timings taken on the library's stream;
+FP64 MFMA roofline from HIP-event timings taken on the library's stream
+around every launch of a 300-step pass that follows each throughput run (the
+events cost ~10% of a small step, so throughput is timed without them);
 `cpu_baseline` is the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
@@ -31,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad"]
+PROFILE_STEPS = 300   # steps of the HIP-event-timed pass after each throughput run
 HEADLINE_VARIANTS = [("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True),
                      ("fp16", True)]
 LARGEST_VARIANTS = [("fp64", True), ("bf16", False), ("bf16", True), ("fp16", True)]
@@ -152,8 +155,12 @@ def cpu_baseline(inp, wk0, key, delta, seconds: float):
                       f"{el:.1f} s on the host"}
 
 
-def run_variant(inp, precision, grad, state, K, W, profile):
-    """Replay the burned-in trajectory for W + K steps; time the last K."""
+def run_variant(inp, precision, grad, state, K, W, Kp):
+    """Replay the burned-in trajectory: W warmup steps, K timed steps, then Kp
+    more steps with HIP-event timing of the GEMM kernels (recording events
+    around every launch costs ~10% of a small step, so it stays out of the
+    throughput region).  Returns (elapsed of the K steps, per-step values of
+    the K steps, per-kernel event totals over the Kp steps)."""
     import torch
 
     from paper_2203_05632_amd import Context
@@ -182,14 +189,17 @@ def run_variant(inp, precision, grad, state, K, W, profile):
     for i in range(W):
         one(step + i, scratch)
     torch.cuda.synchronize()
-    if profile:
-        ctx.profile_begin(PROFILED, K * len(PROFILED))
     t0 = time.perf_counter()
     for i in range(K):
         one(step + W + i, hist[i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = ctx.profile_end() if profile else {}
+    prof = {}
+    if Kp > 0:
+        ctx.profile_begin(PROFILED, Kp * len(PROFILED))
+        for i in range(Kp):
+            one(step + W + K + i, scratch)
+        prof = ctx.profile_end()
     ctx.close()
     return elapsed, hist.mean(dim=1)[:, 2].cpu().numpy(), prof
 
@@ -296,7 +306,8 @@ def measure_workload(name, K, W, n_burn, variants, Kv=None, grad_steps=None):
     wk0 = initial_walkers(inp)
     state = burn_in(inp, wk0, key, n_burn)
     progress(f"{name}: inputs ready, burn-in done")
-    elapsed, ref_vals, prof = run_variant(inp, "fp64", False, state, K, W, profile=True)
+    Kp = min(K, PROFILE_STEPS)
+    elapsed, ref_vals, prof = run_variant(inp, "fp64", False, state, K, W, Kp)
     steps_per_s = K / elapsed
     progress(f"{name} fp64: {steps_per_s:.2f} steps/s")
     sbar = blocking(ref_vals, 100)[1] if K >= 200 else None
@@ -305,24 +316,25 @@ def measure_workload(name, K, W, n_burn, variants, Kv=None, grad_steps=None):
     roofline = None
     if "green_contract" in prof:
         tot_ms, n_l = prof["green_contract"]
-        avg_s = tot_ms / K / 1e3                      # per step (one launch per group of <= 4 tau)
+        avg_s = tot_ms / Kp / 1e3                     # per step (one launch per step)
         ach = flops / avg_s / 1e12
         roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                     "frac": round(ach / PEAK_TFLOPS["fp64"], 4), "traffic": recorded_traffic(name),
                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                     "kernel": "green_contract",
-                    "avg_us": round(tot_ms / n_l * 1e3, 2), "launches_per_step": n_l // K,
-                    "flops_per_launch": flops / (n_l // K)}
+                    "avg_us": round(tot_ms / n_l * 1e3, 2), "launches_per_step": n_l // Kp,
+                    "flops_per_launch": flops / (n_l // Kp), "event_steps": Kp}
     out_vars = {}
     for prec, grad in variants:
         Kn = (grad_steps if (grad and prec == "fp64" and grad_steps) else (Kv or K))
-        el, vals, vprof = run_variant(inp, prec, grad, state, Kn, W, profile=True)
+        Kpn = min(Kn, PROFILE_STEPS)
+        el, vals, vprof = run_variant(inp, prec, grad, state, Kn, W, Kpn)
         vname = prec + ("+grad" if grad else "")
         v = {"steps": Kn, "steps_per_s": round(Kn / el, 2), "ms_per_step": round(1e3 * el / Kn, 5),
              "speedup_vs_fp64": round((Kn / el) / steps_per_s, 3)}
         if grad and "fp64+grad" in out_vars:
             v["speedup_vs_fp64_grad"] = round((Kn / el) / out_vars["fp64+grad"]["steps_per_s"], 3)
-        v["kernels"] = kernel_table(vprof, kflops, Kn, prec)
+        v["kernels"] = kernel_table(vprof, kflops, Kpn, prec)
         if Kn == K and Kn >= 200:
             d = vals - ref_vals
             v["systematic_over_sigma"] = float(f"{abs(d.mean()) / sbar:.3e}")
@@ -332,7 +344,7 @@ def measure_workload(name, K, W, n_burn, variants, Kv=None, grad_steps=None):
     return {"inp": inp, "wk0": wk0, "key": key, "delta": state["delta"], "elapsed": elapsed, "ref_vals": ref_vals,
             "sbar": sbar, "roofline": roofline,
             "fp64": {"steps": K, "steps_per_s": round(steps_per_s, 2), "ms_per_step": round(1e3 * elapsed / K, 5),
-                     "kernels": kernel_table(prof, kflops, K, "fp64")},
+                     "kernels": kernel_table(prof, kflops, Kp, "fp64")},
             "variants": out_vars}
 
 

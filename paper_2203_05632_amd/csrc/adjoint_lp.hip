@@ -28,11 +28,16 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int AK = 32;    // complex K values (y) per LDS chunk
-constexpr int AROW = 36;  // LDS row length in 32-bit words: 32 + 4 padding (144 B)
+constexpr int AK = 32;    // complex K values (y) per LDS chunk: one 128-B LDS row
 constexpr int ABM = 128;  // rows x per block (two row waves of 64)
 
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// LDS rows of 128 B hold eight 16-byte units; unit c of row r sits at slot
+// c ^ (r & 7), so 16-byte reads of one unit from 8 consecutive rows, and the
+// row-wise writes of the staging, touch distinct banks (measured on gfx950 with
+// the SQ_LDS_BANK_CONFLICT counter; padded 144-byte rows do conflict).
+__device__ inline int swz(int row, int unit) { return row * 8 + (unit ^ (row & 7)); }
 
 // psi (float2 [nsp][R]) times s_t[k] -> V_t[k][y] as packed BF16 pairs.
 __global__ __launch_bounds__(256) void adj_operands_kernel(const float2 *__restrict__ psi,
@@ -66,7 +71,7 @@ __global__ __launch_bounds__(256) void adj_lp_kernel(
     constexpr int BN = 2 * WN, NJ = WN / 16;
     constexpr int NA = ABM * (AK / 4) / 256;  // 16-byte A units per thread per chunk
     constexpr int NB = BN * (AK / 4) / 256;   // 16-byte B units per thread per chunk
-    __shared__ __align__(16) uint32_t lds[2][(ABM + BN) * AROW];
+    __shared__ __align__(16) uint32_t lds[2][(ABM + BN) * AK];
     __shared__ float dpart[2][BN];
 
     const int per = (n_items + 7) / 8;
@@ -104,11 +109,11 @@ __global__ __launch_bounds__(256) void adj_lp_kernel(
     auto lstore = [&](int buf) {
         for (int j = 0; j < NA; ++j) {
             const int u = tid + 256 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf][(u / 8) * AROW + 4 * (u % 8)]) = ra[j];
+            *reinterpret_cast<u32x4 *>(&lds[buf][4 * swz(u / 8, u % 8)]) = ra[j];
         }
         for (int j = 0; j < NB; ++j) {
             const int u = tid + 256 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf][(ABM + u / 8) * AROW + 4 * (u % 8)]) = rb[j];
+            *reinterpret_cast<u32x4 *>(&lds[buf][4 * swz(ABM + u / 8, u % 8)]) = rb[j];
         }
     };
 
@@ -124,15 +129,15 @@ __global__ __launch_bounds__(256) void adj_lp_kernel(
     for (int c = 0; c < n_chunks; ++c) {
         const int buf = c & 1;
         if (c + 1 < n_chunks) gload(c + 1);
-        const uint32_t *la = &lds[buf][(64 * wr + li) * AROW + 4 * lk];
-        const uint32_t *lb = &lds[buf][(ABM + WN * wc + li) * AROW + 4 * lk];
+        const uint32_t *l = lds[buf];
 #pragma unroll
-        for (int ks = 0; ks < AK; ks += 16) {
+        for (int ks = 0; ks < AK / 4; ks += 4) {  // 16-byte units: lane group lk reads unit ks + lk
             u32x4 a[4];
-            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(la + 16 * i * AROW + ks);
+            for (int i = 0; i < 4; ++i)
+                a[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, ks + lk));
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
-                const u32x4 b = *reinterpret_cast<const u32x4 *>(lb + 16 * j * AROW + ks);
+                const u32x4 b = *reinterpret_cast<const u32x4 *>(l + 4 * swz(ABM + WN * wc + 16 * j + li, ks + lk));
                 u32x4 br, bi;
                 for (int q = 0; q < 4; ++q) {
                     br[q] = b[q] ^ 0x80000000u;             // (Vr, -Vi)

@@ -256,8 +256,13 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
 // LDS (FP32) two walkers at a time and runs the FP64 pair contraction.
 constexpr int BW = 16;          // walkers per big tile side
 constexpr int BT = 8 * BW;      // rows per big tile side
-constexpr int BKW = 32;         // 32-bit words (one complex operand each) per row per chunk
-constexpr int BROW = BKW + 4;   // padded LDS row in words (144 B)
+constexpr int BKW = 32;         // 32-bit words (one complex operand each) per row per chunk: one 128-B LDS row
+
+// LDS rows of 128 B hold eight 16-byte units; unit c of row r sits at slot
+// c ^ (r & 7), so 16-byte reads of one unit from 8 consecutive rows, and the
+// row-wise writes of the staging, touch distinct banks (measured on gfx950 with
+// the SQ_LDS_BANK_CONFLICT counter; padded 144-byte rows do conflict).
+__device__ inline int swz(int row, int unit) { return row * 8 + (unit ^ (row & 7)); }
 
 template <typename T>
 __device__ inline f4v mfma_pair(u32x4 a, u32x4 b, f4v c) {
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
                                                         int m, double *__restrict__ partial,
                                                         uint32_t *__restrict__ Hm, uint32_t *__restrict__ Hp,
                                                         double cgrad) {
-    constexpr int STAGE = 2 * BT * BROW;  // words per stage: A rows then B rows
+    constexpr int STAGE = 2 * BT * BKW;  // words per stage: A rows then B rows
     __shared__ __align__(16) uint32_t lds[2 * STAGE];
     const int per = (n_items + 7) / 8;
     const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -295,14 +300,18 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
         const int grow = row < BT ? BT * P + row : BT * Q + (row - BT);
         src[j] = Ut + (size_t)min(grow, R - 1) * Ktw + 4 * (u & 7);
     }
-    u32x4 rg[4];
-    auto gload = [&](int w0) __attribute__((always_inline)) {
+    // Two register stages: the loads of chunk c + 2 are issued while chunk c
+    // is multiplied and chunk c + 1 (loaded one iteration earlier) goes to LDS.
+    // Past the last chunk the loads re-read it (branch-free, so the waits the
+    // compiler inserts cover only the older stage).
+    u32x4 ra[4], rb[4];
+    auto gload = [&](u32x4(&rg)[4], int w0) __attribute__((always_inline)) {
         for (int j = 0; j < 4; ++j) rg[j] = *reinterpret_cast<const u32x4 *>(src[j] + w0);
     };
-    auto lstore = [&](int buf) __attribute__((always_inline)) {
+    auto lstore = [&](const u32x4(&rg)[4], int buf) __attribute__((always_inline)) {
         for (int j = 0; j < 4; ++j) {
             const int u = tid + 512 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + (u >> 3) * BROW + 4 * (u & 7)]) = rg[j];
+            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + 4 * swz(u >> 3, u & 7)]) = rg[j];
         }
     };
     f4v gm_re[4][2], gm_im[4][2], gp_re[4][2], gp_im[4][2];
@@ -310,15 +319,15 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
         for (int j = 0; j < 2; ++j) gm_re[i][j] = gm_im[i][j] = gp_re[i][j] = gp_im[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     // G(x, y) = sum_k U_x conj(U_y): Re = U_x . U_y, Im = U_x . (-Im U_y, Re U_y)
     auto chunk = [&](int buf, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
-        const uint32_t *la = &lds[buf * STAGE + (64 * wr + li) * BROW + 4 * lk];
-        const uint32_t *lb = &lds[buf * STAGE + (BT + 32 * wc + li) * BROW + 4 * lk];
+        const uint32_t *l = &lds[buf * STAGE];
 #pragma unroll
-        for (int ks = 0; ks < BKW; ks += 16) {
+        for (int ks = 0; ks < BKW / 4; ks += 4) {  // 16-byte units: lane group lk reads unit ks + lk
             u32x4 a[4];
-            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(la + 16 * i * BROW + ks);
+            for (int i = 0; i < 4; ++i)
+                a[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, ks + lk));
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const u32x4 b = *reinterpret_cast<const u32x4 *>(lb + 16 * j * BROW + ks);
+                const u32x4 b = *reinterpret_cast<const u32x4 *>(l + 4 * swz(BT + 32 * wc + 16 * j + li, ks + lk));
                 u32x4 w;
                 for (int q = 0; q < 4; ++q) w[q] = ((b[q] >> 16) | (b[q] << 16)) ^ 0x8000u;
                 for (int i = 0; i < 4; ++i) {
@@ -331,14 +340,20 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
     auto stream = [&](int w_lo, int w_hi, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
         const int n = (w_hi - w_lo) / BKW;
         if (n == 0) return;
-        gload(w_lo);
-        lstore(0);
+        auto at = [&](int c) { return w_lo + min(c, n - 1) * BKW; };
+        gload(ra, at(0));
+        gload(rb, at(1));
+        lstore(ra, 0);
         __syncthreads();
-        for (int c = 0; c < n; ++c) {
-            const int buf = c & 1;
-            if (c + 1 < n) gload(w_lo + (c + 1) * BKW);
-            chunk(buf, re, im);
-            if (c + 1 < n) lstore(buf ^ 1);
+        for (int c = 0; c < n; c += 2) {
+            gload(ra, at(c + 2));  // rb holds chunk c + 1
+            chunk(0, re, im);
+            if (c + 1 < n) lstore(rb, 1);
+            __syncthreads();
+            if (c + 1 >= n) break;
+            gload(rb, at(c + 3));  // ra holds chunk c + 2
+            chunk(1, re, im);
+            if (c + 2 < n) lstore(ra, 0);
             __syncthreads();
         }
     };

@@ -31,9 +31,14 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int LKW = 32;        // 32-bit words (two K values each) per row per chunk: 64 K values
-constexpr int LROW = LKW + 4;  // padded LDS row in words (144 B)
+constexpr int LKW = 32;        // 32-bit words (two K values each) per row per chunk: 64 K values, one 128-B LDS row
 constexpr int LBM = 128;       // block tile rows and columns
+
+// LDS rows of 128 B hold eight 16-byte units; unit c of row r sits at slot
+// c ^ (r & 7), so 16-byte reads of one unit from 8 consecutive rows, and the
+// row-wise writes of the staging, touch distinct banks (measured on gfx950 with
+// the SQ_LDS_BANK_CONFLICT counter; padded 144-byte rows do conflict).
+__device__ inline int swz(int row, int unit) { return row * 8 + (unit ^ (row & 7)); }
 
 template <typename T>
 __device__ inline f4v mfma_lp(u32x4 a, u32x4 b, f4v c) {
@@ -56,7 +61,7 @@ __device__ __attribute__((always_inline)) inline void lp_gemm_tile(const T *__re
                                                                    int a_rows, const T *__restrict__ B, int ldb,
                                                                    int b_row0, int b_rows, int K, uint32_t *lds,
                                                                    f4v (&acc)[4][4]) {
-    constexpr int STAGE = 2 * LBM * LROW;
+    constexpr int STAGE = 2 * LBM * LKW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
     // staging unit u = tid + 256 j (j < 8): stage row u / 8 (A rows, then B rows), words 4 (u % 8) ..
@@ -77,7 +82,7 @@ __device__ __attribute__((always_inline)) inline void lp_gemm_tile(const T *__re
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int u = tid + 256 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + (u >> 3) * LROW + 4 * (u & 7)]) = rg[j];
+            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + 4 * swz(u >> 3, u & 7)]) = rg[j];
         }
     };
     for (int i = 0; i < 4; ++i)
@@ -90,15 +95,15 @@ __device__ __attribute__((always_inline)) inline void lp_gemm_tile(const T *__re
     for (int c = 0; c < n; ++c) {
         const int buf = c & 1;
         if (c + 1 < n) gload((c + 1) * LKW);
-        const uint32_t *la = &lds[buf * STAGE + (64 * wr + li) * LROW + 4 * lk];
-        const uint32_t *lb = &lds[buf * STAGE + (LBM + 64 * wc + li) * LROW + 4 * lk];
+        const uint32_t *l = &lds[buf * STAGE];
 #pragma unroll
-        for (int ks = 0; ks < LKW; ks += 16) {
+        for (int ks = 0; ks < LKW / 4; ks += 4) {  // 16-byte units: lane group lk reads unit ks + lk
             u32x4 a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(la + 16 * i * LROW + ks);
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, ks + lk));
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const u32x4 *>(lb + 16 * j * LROW + ks);
+            for (int j = 0; j < 4; ++j)
+                b[j] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(LBM + 64 * wc + 16 * j + li, ks + lk));
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -187,7 +192,7 @@ __device__ inline int xcd_item(int n_items) {
 __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict__ Cb, const __bf16 *__restrict__ Xb,
                                                         int nsp, int nLp, int nSp, int E, int R, int n_rt, int n_ct,
                                                         float2 *__restrict__ psi) {
-    __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LROW];
+    __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LKW];
     const int n_items = 2 * n_rt * n_ct;
     const int item = xcd_item(n_items);
     if (item >= n_items) return;
@@ -217,7 +222,7 @@ __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict
 __global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restrict__ XTb, const __bf16 *__restrict__ PBb,
                                                            int nb, int nL, int nsp, int Ep, int n_rt_L, int n_rt_S,
                                                            int n_ct, double *__restrict__ grad_coeffs) {
-    __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LROW];
+    __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LKW];
     const int n_items = (n_rt_L + n_rt_S) * n_ct;
     const int item = xcd_item(n_items);
     if (item >= n_items) return;
