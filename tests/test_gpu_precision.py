@@ -8,7 +8,8 @@ accumulation; scalings, weights, contractions and sums in FP64).
   type (the split-BF16 spinor GEMM adds about 2^-16), and a pair term has
   degree 8 in the spinor values: bound 8 u for unit roundoff u = 2^-8 (BF16),
   2^-11 (FP16).  FP32 mode: bound 1e-6 (about 17 u).
-* Over a chain: the systematic error -- mean over steps of the paired
+* Over a chain (1000 steps of the 340-spinor workload and of the 980-spinor
+  precision workload): the systematic error -- mean over steps of the paired
   difference low - FP64 on the same walker trajectory (valid because the
   walker weights do not depend on the operand precision) -- must stay below
   1% of the FP64 estimator's blocking standard error.
@@ -57,39 +58,59 @@ def test_low_precision_step_near_oracle(prec, name, over, taus):
         assert err < BOUND[prec]
 
 
-@pytest.fixture(scope="module")
-def chain_runs():
-    """One C1 trajectory (1000 steps, 2 tau each) evaluated in every mode."""
+def _chain(name, n_burn, n, delta, key):
+    """One trajectory evaluated in every mode on the same walkers and tau
+    (the walker weights do not depend on the operand precision)."""
     from paper_2203_05632_amd import Context
-    inp = make_inputs("C1")
+    inp = make_inputs(name)
     ctxs = {p: Context.from_inputs(inp, precision=p) for p in ("fp64", "fp32", "bf16", "fp16")}
     drv = ctxs["fp64"]
     wk = dev(initial_walkers(inp))
     w = torch.zeros(inp.m, dtype=torch.float64, device="cuda")
     drv.pair_weights(wk, w)
     tau = torch.zeros(inp.n_tau, dtype=torch.float64, device="cuda")
-    n_burn, n = 200, 1000
     for s in range(n_burn):
-        drv.metropolis(wk, w, (1, 0), s, 0.45)
+        drv.metropolis(wk, w, key, s, delta)
     hist = {p: torch.zeros((n, inp.n_tau, 3), dtype=torch.float64, device="cuda") for p in ctxs}
     for i in range(n):
-        drv.advance(wk, w, (1, 0), n_burn + i, 0.45, tau)
+        drv.advance(wk, w, key, n_burn + i, delta, tau)
         for p, c in ctxs.items():
             c.step(wk, tau, hist[p][i])
     torch.cuda.synchronize()
     return {p: h.mean(dim=1).cpu().numpy()[:, 2] for p, h in hist.items()}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
-def test_systematic_error_below_one_percent_of_sigma(chain_runs, prec):
-    ref = chain_runs["fp64"]
-    d = chain_runs[prec] - ref
+@pytest.fixture(scope="module")
+def chain_runs():
+    """The 340-spinor workload (m = 128, 2 tau per step): 1000 steps."""
+    return _chain("C1", 200, 1000, 0.45, (1, 0))
+
+
+@pytest.fixture(scope="module")
+def chain_runs_c3():
+    """The precision workload (980 spinors, m = 256, 1 tau per step): 1000 steps."""
+    return _chain("C3", 100, 1000, 0.3, (2, 0))
+
+
+def _check_systematic(runs, prec, label):
+    ref = runs["fp64"]
+    d = runs[prec] - ref
     _, sbar = blocking(ref, 100)
     mean_d = float(d.mean())
     _, se_d = blocking(d, 100)
-    print(f"{prec}: systematic {mean_d:.3e} +- {se_d:.3e}, sigma_bar(FP64) {sbar:.3e}, "
+    print(f"{label} {prec}: systematic {mean_d:.3e} +- {se_d:.3e}, sigma_bar(FP64) {sbar:.3e}, "
           f"ratio {abs(mean_d) / sbar:.2e}", flush=True)
     assert abs(mean_d) < 0.01 * sbar
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_systematic_error_below_one_percent_of_sigma(chain_runs, prec):
+    _check_systematic(chain_runs, prec, "C1")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_systematic_error_below_one_percent_of_sigma_precision_workload(chain_runs_c3, prec):
+    _check_systematic(chain_runs_c3, prec, "C3")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
