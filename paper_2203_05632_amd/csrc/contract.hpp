@@ -1,23 +1,44 @@
-// Per-walker-pair contraction of the MC-MP2 integrand from 16x16 G tiles in
-// LDS (shared by the FP64 and the low-precision Green's-function kernels;
-// all of it runs in FP64).  See green.hip for the definitions.
+// Per-walker-pair contraction of the MC-MP2 integrand from G tiles in LDS
+// (shared by the FP64 and the low-precision Green's-function kernels).  See
+// green.hip for the definitions.
 #pragma once
 
 #include "internal.hpp"
 
-struct cplx {
-    double re, im;
+// complex numbers in the contraction's arithmetic type F (FP64, or FP32 in
+// the BF16 / FP16 modes)
+template <typename F>
+struct cx {
+    F re, im;
 };
-__device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ inline cplx cmulc(cplx a, cplx b) {  // conj(a) * b
+using cplx = cx<double>;
+template <typename F>
+__device__ inline cx<F> cmul(cx<F> a, cx<F> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename F>
+__device__ inline cx<F> cmulc(cx<F> a, cx<F> b) {  // conj(a) * b
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
-__device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
-__device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
-__device__ inline cplx conjc(cplx a) { return {a.re, -a.im}; }
-__device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
-__device__ inline cplx shfl_xor_c(cplx a, int mask) {
+template <typename F>
+__device__ inline cx<F> cadd(cx<F> a, cx<F> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <typename F>
+__device__ inline cx<F> csub(cx<F> a, cx<F> b) {
+    return {a.re - b.re, a.im - b.im};
+}
+template <typename F>
+__device__ inline cx<F> conjc(cx<F> a) {
+    return {a.re, -a.im};
+}
+template <typename F>
+__device__ inline cx<F> shfl_xor_c(cx<F> a, int mask) {
     return {__shfl_xor(a.re, mask, 64), __shfl_xor(a.im, mask, 64)};
+}
+template <typename F>
+__device__ inline cx<F> shfl_c(cx<F> a, int src) {
+    return {__shfl(a.re, src, 64), __shfl(a.im, src, 64)};
 }
 
 // Adjoint-block element stores: FP64 complex, or a BF16 pair packed in 32
@@ -29,32 +50,39 @@ __device__ inline void h_store(uint32_t *H, size_t i, double re, double im) {
 }
 
 
-__device__ inline cplx to_c(const cplx &v) { return v; }
-__device__ inline cplx to_c(const float2 &v) { return {(double)v.x, (double)v.y}; }
+template <typename F>
+__device__ inline cx<F> to_cx(const cplx &v) {
+    return {(F)v.re, (F)v.im};
+}
+template <typename F>
+__device__ inline cx<F> to_cx(const float2 &v) {
+    return {(F)v.x, (F)v.y};
+}
 
 // One walker pair (p, q) per 16 lanes (lane & 15 = 4 a + b: indices of the
 // 4x4 blocks).  Gm / Gp: element (e, i; f, j) of the pair's G- / G+ block
 // (rows 8 p + 4 e + i, columns 8 q + 4 f + j) at [(4 e + i) ld + 4 f + j]
-// (complex FP64 or FP32; the arithmetic is FP64).  Returns the pair's
-// weighted direct and exchange terms (zero unless ok) in every lane of the
-// group and, with GRAD, writes the pair's adjoint blocks and their
+// (complex FP64 or FP32).  The traces and block products run in F; the
+// weight 1/(w_p w_q w_tau) and everything after it in FP64.  Returns the
+// pair's weighted direct and exchange terms (zero unless ok) in every lane of
+// the group and, with GRAD, writes the pair's adjoint blocks and their
 // Hermitian partners into Hm / Hp (R x R, this tau; HT = double2, or
 // uint32_t for BF16 pairs).
-template <bool GRAD, typename HT, typename GT>
+template <bool GRAD, typename HT, typename F, typename GT>
 __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, int q, bool ok,
                                      const double *__restrict__ hinv, double wt, double cgrad, int R, double &dir,
                                      double &exc, HT *__restrict__ Hm, HT *__restrict__ Hp) {
     const int lane = threadIdx.x & 63;
     const int a = (lane & 15) >> 2, b = lane & 3;
-#define GB(G, e, f, i, j) to_c(G[(4 * (e) + (i)) * ld + 4 * (f) + (j)])
-    cplx t1 = cmulc(GB(Gm, 0, 0, a, b), GB(Gp, 0, 0, a, b));
-    cplx t2 = cmulc(GB(Gm, 1, 1, a, b), GB(Gp, 1, 1, a, b));
-    cplx m1 = {0.0, 0.0}, m2 = {0.0, 0.0};
+#define GB(G, e, f, i, j) to_cx<F>(G[(4 * (e) + (i)) * ld + 4 * (f) + (j)])
+    cx<F> t1 = cmulc(GB(Gm, 0, 0, a, b), GB(Gp, 0, 0, a, b));
+    cx<F> t2 = cmulc(GB(Gm, 1, 1, a, b), GB(Gp, 1, 1, a, b));
+    cx<F> m1 = {0, 0}, m2 = {0, 0};
     for (int k = 0; k < 4; ++k) {
         m1 = cadd(m1, cmulc(GB(Gm, 0, 0, k, a), GB(Gp, 0, 1, k, b)));  // [G-(1,3)^H G+(1,4)]_{ab}
         m2 = cadd(m2, cmulc(GB(Gm, 1, 1, k, b), GB(Gp, 1, 0, k, a)));  // [G-(2,4)^H G+(2,3)]_{ba}
     }
-    cplx xt = cmul(m1, m2);
+    cx<F> xt = cmul(m1, m2);
     for (int mask = 8; mask >= 1; mask >>= 1) {
         t1 = cadd(t1, shfl_xor_c(t1, mask));
         t2 = cadd(t2, shfl_xor_c(t2, mask));
@@ -63,9 +91,9 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
     dir = exc = 0.0;
     if (ok) {
         const double W = hinv[p] * hinv[q] / wt;
-        const cplx D = cmul(t1, t2);
-        dir = -0.5 * D.re * W;
-        exc = 0.5 * xt.re * W;
+        const cx<F> D = cmul(t1, t2);
+        dir = -0.5 * (double)D.re * W;
+        exc = 0.5 * (double)xt.re * W;
         if constexpr (GRAD) {
             // Adjoint of c Re(t1 t2 - X), c = cgrad W, with the stored blocks
             // A13 = G-(1,3), A24 = G-(2,4), P13 = G+(1,3), P14, P23, P24
@@ -78,45 +106,37 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
             // The triple products as (X Y^H) Z: lane (a, b) forms [X Y^H]_{ab}
             // (four terms), then row a of it is gathered from lanes 4 a + l of
             // the pair's group for the product with Z.
-            cplx x13 = {0.0, 0.0}, x24 = {0.0, 0.0}, x14 = {0.0, 0.0}, x23 = {0.0, 0.0};
+            cx<F> x13 = {0, 0}, x24 = {0, 0}, x14 = {0, 0}, x23 = {0, 0};
             for (int k = 0; k < 4; ++k) {
                 x13 = cadd(x13, cmul(GB(Gp, 0, 1, a, k), conjc(GB(Gm, 1, 1, b, k))));  // P14 A24^H
                 x24 = cadd(x24, cmul(GB(Gp, 1, 0, a, k), conjc(GB(Gm, 0, 0, b, k))));  // P23 A13^H
                 x14 = cadd(x14, cmul(GB(Gm, 0, 0, a, k), conjc(GB(Gp, 1, 0, b, k))));  // A13 P23^H
                 x23 = cadd(x23, cmul(GB(Gm, 1, 1, a, k), conjc(GB(Gp, 0, 1, b, k))));  // A24 P14^H
             }
-            cplx s13 = {0.0, 0.0}, s24 = {0.0, 0.0}, s14 = {0.0, 0.0}, s23 = {0.0, 0.0};
+            cx<F> s13 = {0, 0}, s24 = {0, 0}, s14 = {0, 0}, s23 = {0, 0};
             const int row0 = lane & ~3;
             for (int l = 0; l < 4; ++l) {
                 const int src = row0 | l;
-                const cplx y13 = {__shfl(x13.re, src, 64), __shfl(x13.im, src, 64)};
-                const cplx y24 = {__shfl(x24.re, src, 64), __shfl(x24.im, src, 64)};
-                const cplx y14 = {__shfl(x14.re, src, 64), __shfl(x14.im, src, 64)};
-                const cplx y23 = {__shfl(x23.re, src, 64), __shfl(x23.im, src, 64)};
-                s13 = cadd(s13, cmul(y13, GB(Gp, 1, 0, l, b)));  // (P14 A24^H) P23
-                s24 = cadd(s24, cmul(y24, GB(Gp, 0, 1, l, b)));  // (P23 A13^H) P14
-                s14 = cadd(s14, cmul(y14, GB(Gm, 1, 1, l, b)));  // (A13 P23^H) A24
-                s23 = cadd(s23, cmul(y23, GB(Gm, 0, 0, l, b)));  // (A24 P14^H) A13
+                s13 = cadd(s13, cmul(shfl_c(x13, src), GB(Gp, 1, 0, l, b)));  // (P14 A24^H) P23
+                s24 = cadd(s24, cmul(shfl_c(x24, src), GB(Gp, 0, 1, l, b)));  // (P23 A13^H) P14
+                s14 = cadd(s14, cmul(shfl_c(x14, src), GB(Gm, 1, 1, l, b)));  // (A13 P23^H) A24
+                s23 = cadd(s23, cmul(shfl_c(x23, src), GB(Gm, 0, 0, l, b)));  // (A24 P14^H) A13
             }
-            const cplx p13 = GB(Gp, 0, 0, a, b), p24 = GB(Gp, 1, 1, a, b);
-            const cplx a13 = GB(Gm, 0, 0, a, b), a24 = GB(Gm, 1, 1, a, b);
-            const cplx hm13 = cscale(csub(cmul(t2, p13), s13), cw);
-            const cplx hm24 = cscale(csub(cmul(t1, p24), s24), cw);
-            const cplx hp13 = cscale(cmul(conjc(t2), a13), cw);
-            const cplx hp24 = cscale(cmul(conjc(t1), a24), cw);
-            const cplx hp14 = cscale(s14, -cw);
-            const cplx hp23 = cscale(s23, -cw);
+            const cx<F> p13 = GB(Gp, 0, 0, a, b), p24 = GB(Gp, 1, 1, a, b);
+            const cx<F> a13 = GB(Gm, 0, 0, a, b), a24 = GB(Gm, 1, 1, a, b);
             const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
-            auto put = [&](HT *H, size_t r, size_t cc, cplx v) {
-                h_store(H, r * R + cc, v.re, v.im);
-                h_store(H, cc * R + r, v.re, -v.im);  // Hermitian partner block (q, p)
+            // element (r, cc) = scale * v, its Hermitian partner (cc, r) = conj
+            auto put = [&](HT *H, size_t r, size_t cc, cx<F> v, double scale) {
+                const double re = (double)v.re * scale, im = (double)v.im * scale;
+                h_store(H, r * R + cc, re, im);
+                h_store(H, cc * R + r, re, -im);
             };
-            put(Hm, r1, c3, hm13);
-            put(Hm, r2, c4, hm24);
-            put(Hp, r1, c3, hp13);
-            put(Hp, r2, c4, hp24);
-            put(Hp, r1, c4, hp14);
-            put(Hp, r2, c3, hp23);
+            put(Hm, r1, c3, csub(cmul(t2, p13), s13), cw);
+            put(Hm, r2, c4, csub(cmul(t1, p24), s24), cw);
+            put(Hp, r1, c3, cmul(conjc(t2), a13), cw);
+            put(Hp, r2, c4, cmul(conjc(t1), a24), cw);
+            put(Hp, r1, c4, s14, -cw);
+            put(Hp, r2, c3, s23, -cw);
         }
     }
 #undef GB
@@ -128,7 +148,7 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
 // is (wp, wq) = (wave >> 1, wave & 1)).  16 lanes per walker pair: (pp, qq) =
 // walker offsets in the sub-tile.  Writes the wave's direct and exchange
 // sums to out[0], out[1] and, with GRAD, the pairs' adjoint blocks.
-template <bool GRAD, typename HT>
+template <bool GRAD, typename HT, typename F = double>
 __device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, int QT, int m,
                                       const double *__restrict__ hinv, double wt, double cgrad, int R,
                                       double *__restrict__ out, HT *__restrict__ Hm, HT *__restrict__ Hp) {
@@ -137,8 +157,8 @@ __device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, in
     const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
     const int p = kTileWalkers * PT + 2 * wp + pp, q = kTileWalkers * QT + 2 * wq + qq;
     double dir, exc;
-    contract_pair<GRAD, HT>(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv,
-                            wt, cgrad, R, dir, exc, Hm, Hp);
+    contract_pair<GRAD, HT, F>(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m,
+                                    hinv, wt, cgrad, R, dir, exc, Hm, Hp);
     // pairs of this wave summed in a fixed order (lanes 0, 16, 32, 48)
     const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
                  d3 = __shfl(dir, 48, 64);

@@ -238,7 +238,9 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
             Gp[i * 16 + li] = {(double)gp_re[t][v], (double)gp_im[t][v]};
         }
         __syncthreads();
-        contract_pairs<GRAD, HT>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
+        // FP32 contraction arithmetic with BF16 / FP16 operands, FP64 with FP32 operands
+        contract_pairs<GRAD, HT, std::conditional_t<sizeof(T) == 2, float, double>>(Gm, Gp, PT, QT, m, hinv,
+                                                                                   wtau[t0 + t], cgrad, R,
                              partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
                              GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
                              GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
             const int pi = 4 * r + lk, pr = pi >> 2, qc = pi & 3;
             const int p = BW * P + 8 * wr + 2 * i + pr, q = BW * Q + 4 * wc + qc;
             double dir, exc;
-            contract_pair<GRAD, uint32_t>(Gm + 8 * pr * 32 + 8 * qc, Gp + 8 * pr * 32 + 8 * qc, 32, p, q,
+            contract_pair<GRAD, uint32_t, float>(Gm + 8 * pr * 32 + 8 * qc, Gp + 8 * pr * 32 + 8 * qc, 32, p, q,
                                           p < q && q < m, hinv, wt, cgrad, R, dir, exc, Hm_t, Hp_t);
             const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
                          d3 = __shfl(dir, 48, 64);

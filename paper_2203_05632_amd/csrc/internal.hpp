@@ -62,8 +62,10 @@ struct mcmp2_ctx {
     int *tiles16 = nullptr;   // [n_tp16][2] (P, Q) in 4 x 8 patches
     double *partial = nullptr;  // [n_tau_max][max(n_slots, 8 n_tp16)][2] per wave slot (direct, exchange)
     // gradient work space (allocated when want_grad)
-    double *Hm = nullptr;       // [n_tau_max][R][R] complex adjoint of G-
-    double *Hp = nullptr;       // [n_tau_max][R][R] complex adjoint of G+
+    // adjoint blocks [n_tau_max][R][R]: complex FP64 (FP64, FP32 modes) or
+    // packed BF16 pairs, real part in the low half (BF16, FP16 modes)
+    double *Hm = nullptr;       // adjoint of G-
+    double *Hp = nullptr;       // adjoint of G+
     double *psibar = nullptr;   // [nsp][R] complex gradient of psi
     uint32_t *Vt = nullptr;     // BF16 / FP16 modes: [n_tau_max][nsp][R] psi s_t as packed BF16 pairs
     // BF16 / FP16 modes: BF16 operands of the spinor GEMM and the coefficient
@@ -74,7 +76,7 @@ struct mcmp2_ctx {
     void *Xb = nullptr;   // [E][3 nbp] basis values per point, split [hi|lo|hi] per set
     void *XTb = nullptr;  // [nb][Ep] basis values per primitive (gradients)
     void *PBb = nullptr;  // [2 sets][4 nsp][Ep] psi gradient (gradients)
-    double *eps_part = nullptr; // [R / 32][nsp] per row tile
+    double *eps_part = nullptr; // [row tiles][nsp] eps-gradient partials (32-row tiles, or 128-row in BF16 / FP16 modes)
 
     Profiler prof;
 };
