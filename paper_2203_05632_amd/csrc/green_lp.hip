@@ -362,37 +362,42 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
     stream(0, Kow, gm_re, gm_im);
     stream(Kow, Ktw, gp_re, gp_im);
 
-    // epilogue: wave-private G rows in LDS, 16 rows (two walkers) x 32 columns (four walkers) per pass
+    // epilogue: wave-private G rows in LDS, 8 rows (one walker) x 32 columns
+    // (four walkers) at a time.  Rows are padded to 36 complex (288 B, i.e.
+    // 32 B apart modulo the 256-byte bank row), so the 4-row reads of the
+    // contraction hit each bank at most twice.
+    constexpr int GLD = 36;
     float2 *Gm = reinterpret_cast<float2 *>(lds) + wave * 1024;
-    float2 *Gp = Gm + 512;
+    float2 *Gp = Gm + 8 * GLD;
     uint32_t *Hm_t = GRAD ? Hm + (size_t)t * R * R : nullptr;
     uint32_t *Hp_t = GRAD ? Hp + (size_t)t * R * R : nullptr;
     const double wt = wtau[t];
     double dsum = 0.0, xsum = 0.0;
 #pragma unroll  // constant indices keep the accumulators in registers
-    for (int i = 0; i < 4; ++i) {
-        for (int j = 0; j < 2; ++j)
-            for (int v = 0; v < 4; ++v) {
-                const int e = (4 * lk + v) * 32 + 16 * j + li;  // MFMA result row 4 lk + v, column 16 j + li
-                Gm[e] = float2{gm_re[i][j][v], gm_im[i][j][v]};
-                Gp[e] = float2{gp_re[i][j][v], gp_im[i][j][v]};
-            }
-        __syncthreads();
-        for (int r = 0; r < 2; ++r) {
-            const int pi = 4 * r + lk, pr = pi >> 2, qc = pi & 3;
-            const int p = BW * P + 8 * wr + 2 * i + pr, q = BW * Q + 4 * wc + qc;
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // MFMA result rows 4 lk + v of sub-tile i: walker row h holds lane groups lk = 2 h, 2 h + 1
+            if ((lk >> 1) == h)
+                for (int j = 0; j < 2; ++j)
+                    for (int v = 0; v < 4; ++v) {
+                        const int e = (4 * (lk & 1) + v) * GLD + 16 * j + li;
+                        Gm[e] = float2{gm_re[i][j][v], gm_im[i][j][v]};
+                        Gp[e] = float2{gp_re[i][j][v], gp_im[i][j][v]};
+                    }
+            __syncthreads();
+            const int p = BW * P + 8 * wr + 2 * i + h, q = BW * Q + 4 * wc + lk;
             double dir, exc;
-            contract_pair<GRAD, uint32_t, float>(Gm + 8 * pr * 32 + 8 * qc, Gp + 8 * pr * 32 + 8 * qc, 32, p, q,
-                                          p < q && q < m, hinv, wt, cgrad, R, dir, exc, Hm_t, Hp_t);
+            contract_pair<GRAD, uint32_t, float>(Gm + 8 * lk, Gp + 8 * lk, GLD, p, q, p < q && q < m, hinv, wt, cgrad,
+                                                 R, dir, exc, Hm_t, Hp_t);
             const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
                          d3 = __shfl(dir, 48, 64);
             const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
                          x3 = __shfl(exc, 48, 64);
             dsum += ((d0 + d1) + d2) + d3;
             xsum += ((x0 + x1) + x2) + x3;
+            __syncthreads();
         }
-        __syncthreads();
-    }
     if (lane == 0) {
         double *out = partial + ((size_t)item * 8 + wave) * 2;
         out[0] = dsum;
