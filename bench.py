@@ -36,7 +36,7 @@ PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad"]
 PROFILE_STEPS = 300   # steps of the HIP-event-timed pass after each throughput run
 HEADLINE_VARIANTS = [("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True),
                      ("fp16", True)]
-LARGEST_VARIANTS = [("fp64", True), ("bf16", False), ("bf16", True), ("fp16", True)]
+LARGEST_VARIANTS = [("fp64", True), ("fp32", True), ("bf16", False), ("bf16", True), ("fp16", True)]
 METRIC = "MC steps/s and var×time for E2(+grad), FP32/BF16 vs FP64, 1 MI355X"
 # published dense peaks of one MI355X (TFLOP/s) for the GEMM operand type
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
@@ -218,7 +218,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel for counter calibration)")
     ap.add_argument("--largest-steps", type=int, default=1000, help="timed C4 steps per variant")
-    ap.add_argument("--largest-grad-steps", type=int, default=200, help="timed C4 steps of the FP64 gradient run")
+    ap.add_argument("--largest-grad-steps", type=int, default=200,
+                    help="timed C4 steps of the gradient runs with an FP64 adjoint (FP64, FP32 modes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (one MC chain on one MI355X); --gpus {args.gpus} is not supported",
@@ -249,6 +250,9 @@ def main():
             largest["bf16_grad_over_fp64"] = round(b16["steps_per_s"] / lw["fp64"]["steps_per_s"], 3)
             largest["bf16_grad_green_mfma_frac"] = b16["kernels"]["green_contract"]["peak_frac"]
             largest["bf16_grad_systematic_over_sigma"] = b16.get("systematic_over_sigma")
+        f32 = lw["variants"].get("fp32+grad", {})
+        if f32:
+            largest["fp32_grad_green_mfma_frac"] = f32["kernels"]["green_contract"]["peak_frac"]
 
     cpu = cpu_baseline(inp, head["wk0"], head["key"], head["delta"], args.cpu_seconds) if args.cpu_seconds > 0 \
         else None
@@ -326,7 +330,8 @@ def measure_workload(name, K, W, n_burn, variants, Kv=None, grad_steps=None):
                     "flops_per_launch": flops / (n_l // Kp), "event_steps": Kp}
     out_vars = {}
     for prec, grad in variants:
-        Kn = (grad_steps if (grad and prec == "fp64" and grad_steps) else (Kv or K))
+        # runs with an FP64 adjoint GEMM (FP64 and FP32 modes) are ~10x slower: fewer steps
+        Kn = (grad_steps if (grad and prec in ("fp64", "fp32") and grad_steps) else (Kv or K))
         Kpn = min(Kn, PROFILE_STEPS)
         el, vals, vprof = run_variant(inp, prec, grad, state, Kn, W, Kpn)
         vname = prec + ("+grad" if grad else "")
