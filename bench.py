@@ -32,7 +32,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad"]
+PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad", "accumulate"]
+HBM_PEAK_GBS = 8000.0   # published HBM3E bandwidth of one MI355X
 PROFILE_STEPS = 300   # steps of the HIP-event-timed pass after each throughput run
 HEADLINE_VARIANTS = [("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True),
                      ("fp16", True)]
@@ -99,6 +100,8 @@ def kernel_flops(inp) -> dict:
         "green_contract": green_flops(m, nsp, nt),
         "grad": 512.0 * m * (m - 1) * nsp * nt,      # Psibar = sum_t H_t Psi S_t, off-diagonal walker blocks
         "coef_grad": 16.0 * m * nsp * nb,            # Cbar = X^T Psibar: same shape as the spinor GEMM
+        # compensated accumulation of both gradients per step: 5 doubles moved per element
+        "accumulate_bytes": 5 * 8.0 * (nsp + 2 * 2 * nb * nsp),
     }
 
 
@@ -119,6 +122,11 @@ def kernel_table(prof: dict, kflops: dict, K: int, prec: str) -> dict:
     out = {}
     for k, (tot_ms, _) in prof.items():
         avg_s = tot_ms / K / 1e3
+        if k == "accumulate":   # HBM-bound: reads src, sum, comp and writes sum, comp per element
+            gbs = kflops["accumulate_bytes"] / avg_s / 1e9
+            out[k] = {"us_per_step": round(avg_s * 1e6, 2), "GB_per_s": round(gbs, 1),
+                      "peak_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            continue
         tf = kflops[k] / avg_s / 1e12
         op = operand_type(prec, k)
         out[k] = {"us_per_step": round(avg_s * 1e6, 2), "tflops": round(tf, 2), "operands": op,
@@ -196,7 +204,7 @@ def run_variant(inp, precision, grad, state, K, W, Kp):
     elapsed = time.perf_counter() - t0
     prof = {}
     if Kp > 0:
-        ctx.profile_begin(PROFILED, Kp * len(PROFILED))
+        ctx.profile_begin(PROFILED, Kp * (len(PROFILED) + 2))  # accumulate runs twice per gradient step
         for i in range(Kp):
             one(step + W + K + i, scratch)
         prof = ctx.profile_end()
@@ -215,6 +223,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="FP64 headline only")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0: skip)")
     ap.add_argument("--no-largest", action="store_true", help="skip the largest-workload (C4) section")
+    ap.add_argument("--study", choices=["convergence", "scaling"], default=None,
+                    help="instead of the benchmark: redundant-walker convergence vs m, or cost vs basis size")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel for counter calibration)")
     ap.add_argument("--largest-steps", type=int, default=1000, help="timed C4 steps per variant")
@@ -229,6 +239,10 @@ def main():
     import torch
 
     torch.cuda.set_device(0)
+    if args.study:
+        out = study_convergence(args) if args.study == "convergence" else study_scaling(args)
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -274,6 +288,60 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def study_convergence(args):
+    """Redundant-walker estimator vs the number of walker pairs m (Sec. III:
+    all m(m-1)/2 pairs of m independent walkers enter every step, at a cost
+    per step growing like m^2): for each m, FP64 steps/s, sigma_bar of the
+    step mean (blocking, N_b = 100), the per-step variance sigma_bar^2 N and
+    var x time.  The 340-spinor shapes with basis exponents in [0.3, 1.2]:
+    with the full exponent range and synthetic orbitals the estimator is
+    heavy-tailed and sigma_bar does not settle within a few thousand steps."""
+    from oracle.blocking import blocking
+    from synth import initial_walkers, make_inputs
+    K = max(args.steps, 5000)
+    rows = []
+    for m in (8, 16, 32, 64, 128, 256, 512):
+        inp = make_inputs("C1", m=m, exp_range=(0.3, 1.2))
+        state = burn_in(inp, initial_walkers(inp), (0, m), args.burnin)
+        el, vals, _ = run_variant(inp, "fp64", False, state, K, args.warmup, 0)
+        sb = blocking(vals, 100)[1]
+        rows.append({"m": m, "pairs": m * (m - 1) // 2, "steps": K, "steps_per_s": round(K / el, 2),
+                     "e2_mean": float(f"{vals.mean():.6g}"), "sigma_bar": float(f"{sb:.4g}"),
+                     "var_per_step": float(f"{sb * sb * K:.4g}"), "var_x_time": float(f"{sb * sb * el:.4g}")})
+        progress(f"convergence m={m}: {rows[-1]}")
+    return {"study": "redundant-walker convergence vs m",
+            "workload": "C1 shapes (3 nuclei, 200 L / 460 S primitives, 40 occupied / 300 virtual spinors, "
+                        "2 tau per step) with basis exponents in [0.3, 1.2]",
+            "precision": "fp64", "rows": rows}
+
+
+def study_scaling(args):
+    """Cost per step vs basis size at fixed m = 128 and 1 tau per step, on the
+    synthetic size ladder of the workloads (n_L = 12 ... 1000 primitives,
+    n_sp = 20 ... 1620 spinors): FP64 and BF16 steps/s, with and without
+    gradients, and the log-log slope of time per step against n_b."""
+    import numpy as np
+
+    from synth import initial_walkers, make_inputs
+    K = 200
+    rows = []
+    for name in ("C0", "C1", "C3", "C4"):
+        inp = make_inputs(name, m=128, n_tau=1)
+        state = burn_in(inp, initial_walkers(inp), (0, 0), 50)
+        row = {"workload": name, "n_b": inp.n_b, "n_occ": inp.n_occ, "n_sp": inp.n_sp}
+        for prec, grad in (("fp64", False), ("fp64", True), ("bf16", False), ("bf16", True)):
+            el, _, _ = run_variant(inp, prec, grad, state, K, 10, 0)
+            row[prec + ("+grad" if grad else "")] = round(K / el, 2)
+        rows.append(row)
+        progress(f"scaling {name}: {row}")
+    out = {"study": "cost per step vs basis size (m = 128, 1 tau)", "rows": rows}
+    nb = np.log([r["n_b"] for r in rows[1:]])
+    for key in ("fp64", "fp64+grad", "bf16", "bf16+grad"):
+        t = np.log([1.0 / r[key] for r in rows[1:]])
+        out[f"slope_{key}"] = round(float(np.polyfit(nb, t, 1)[0]), 3)   # d log(time) / d log(n_b), C1..C4
+    return out
 
 
 def burn_in(inp, wk0, key, n_burn):

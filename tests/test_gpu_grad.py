@@ -73,6 +73,21 @@ def test_gradient_invariants_on_gpu():
     assert abs(vir - 4 * V) <= 1e-10 * scale
 
 
+def test_coefficient_gradient_phase_invariance_on_gpu():
+    """V is invariant under psi_k -> e^{i theta} psi_k (every spinor enters G
+    as psi psi^dagger), so Im sum_{s,mu} conj(C[s][mu][k]) Cbar[s][mu][k] = 0
+    for each k; checked in every precision mode."""
+    inp = make_inputs("C1")
+    wk = initial_walkers(inp)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-6), ("bf16", 1e-2), ("fp16", 1e-2)):
+        ctx = _ctx(inp, precision=prec)
+        _, _, gc = _gpu_grad(ctx, inp, wk, np.array([0.4, 1.3]))
+        per_k = np.sum(inp.coeffs.conj() * gc, axis=(0, 1))
+        scale = np.abs(inp.coeffs.conj() * gc).sum(axis=(0, 1)).max()
+        print(f"{prec}: max |Im sum conj(C) Cbar| / scale = {np.abs(per_k.imag).max() / scale:.2e}", flush=True)
+        assert np.abs(per_k.imag).max() <= tol * scale
+
+
 def test_forward_identical_with_and_without_gradient():
     inp = make_inputs("C1")
     wk = initial_walkers(inp)
