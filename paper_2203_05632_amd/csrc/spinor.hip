@@ -334,6 +334,7 @@ hipError_t launch_spinor_tile(const mcmp2_ctx *c) {
 template <typename T>
 hipError_t launch_spinor_typed(const mcmp2_ctx *c) {
     auto items = [&](int ks, int pts) { return 2 * ((c->nsp + ks - 1) / ks) * ((c->E + pts - 1) / pts); };
+    if (items(16, 64) >= 4 * c->n_cu) return launch_spinor_tile<T, 16, 64>(c);
     if (items(32, 128) >= c->n_cu) return launch_spinor_tile<T, 32, 128>(c);
     if (items(16, 64) >= c->n_cu) return launch_spinor_tile<T, 16, 64>(c);
     // latency-bound sizes: 16 x 16 tiles, K split over the block's waves, no LDS staging
