@@ -223,8 +223,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="FP64 headline only")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0: skip)")
     ap.add_argument("--no-largest", action="store_true", help="skip the largest-workload (C4) section")
-    ap.add_argument("--study", choices=["convergence", "scaling"], default=None,
-                    help="instead of the benchmark: redundant-walker convergence vs m, or cost vs basis size")
+    ap.add_argument("--study", choices=["convergence", "scaling", "chains"], default=None,
+                    help="instead of the benchmark: redundant-walker convergence vs m, cost vs basis size, or "
+                         "independent chains on concurrent streams")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel for counter calibration)")
     ap.add_argument("--largest-steps", type=int, default=1000, help="timed C4 steps per variant")
@@ -240,7 +241,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.study:
-        out = study_convergence(args) if args.study == "convergence" else study_scaling(args)
+        out = {"convergence": study_convergence, "scaling": study_scaling, "chains": study_chains}[args.study](args)
         print(json.dumps(out), flush=True)
         return
     if args.copy_mib > 0:
@@ -342,6 +343,42 @@ def study_scaling(args):
         t = np.log([1.0 / r[key] for r in rows[1:]])
         out[f"slope_{key}"] = round(float(np.polyfit(nb, t, 1)[0]), 3)   # d log(time) / d log(n_b), C1..C4
     return out
+
+
+def study_chains(args):
+    """Independent chains (the paper's parallel model, Sec. III) on separate
+    HIP streams of one GPU: aggregate MC steps/s of k = 1, 2, 4, 8 chains of
+    the 340-spinor FP64 workload, launched block by block in turn, and the
+    merged estimate."""
+    import torch
+
+    from paper_2203_05632_amd import Chain, Context, merge
+    from synth import initial_walkers, make_inputs
+    inp = make_inputs("C1")
+    K = max(args.steps, 1000)
+    rows = []
+    for k in (1, 2, 4, 8):
+        streams = [torch.cuda.Stream() for _ in range(k)]
+        chains = [Chain(Context.from_inputs(inp, stream=streams[c]), initial_walkers(inp, chain=c), key=(7, c))
+                  for c in range(k)]
+        for ch in chains:
+            ch.burn_in(args.burnin)
+            ch.run(50, block=50)            # warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K // 100):
+            for ch in chains:
+                ch.run(100, block=100)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res = merge([ch.result() for ch in chains])
+        rows.append({"chains": k, "steps_total": k * (K // 100) * 100, "steps_per_s": round(k * (K // 100) * 100 / el, 1),
+                     "e2_merged": float(f"{res.mean[2]:.6g}"), "sigma_merged": float(f"{res.sigma[2]:.4g}")})
+        progress(f"chains k={k}: {rows[-1]}")
+        for ch in chains:
+            ch.ctx.close()
+    return {"study": "independent chains on concurrent streams", "workload": f"C1 {WORKLOADS['C1']}",
+            "precision": "fp64", "rows": rows}
 
 
 def burn_in(inp, wk0, key, n_burn):

@@ -1,0 +1,83 @@
+"""The chain driver on the GPU: parity of a whole run with the oracle chain,
+bit-identical resume from a checkpoint, and independence of chains run
+concurrently on separate streams."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import requires_gpu
+from synth import initial_walkers, make_inputs
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def _chain(inp, key=(3, 1), want_grad=False, stream=None, **kw):
+    from paper_2203_05632_amd import Chain, Context
+    ctx = Context.from_inputs(inp, want_grad=want_grad, stream=stream, **kw)
+    return Chain(ctx, initial_walkers(inp, chain=key[1]), key=key, delta=0.4, want_grad=want_grad)
+
+
+def test_gpu_chain_matches_oracle_chain():
+    """Whole run (fixed-delta moves, then 200 steps of move + tau + estimator):
+    walker positions bit-identical, per-step values within 1e-10 of the
+    oracle's chain on the same key."""
+    from oracle.chain import Chain as OracleChain
+    inp = make_inputs("C0", n_tau=2)
+    key = (3, 1)
+    ch = _chain(inp, key)
+    ch.burn_in(50, adapt=False)
+    ch.run(200, block=64)
+    ref = OracleChain(inp, initial_walkers(inp, chain=1), key=key, delta=0.4)
+    ref.burn_in(50, adapt=False)
+    ref_vals = ref.run(200, n_tau=2)
+    got = ch.series()
+    scale = np.abs(ref_vals).max()
+    print(f"max per-step deviation / max |value| = {np.abs(got - ref_vals).max() / scale:.2e}", flush=True)
+    assert np.abs(got - ref_vals).max() <= 1e-10 * scale
+    assert np.array_equal(ch.walkers.cpu().numpy(), ref.walkers)
+
+
+@pytest.mark.parametrize("grad", [False, True])
+def test_resume_from_checkpoint_is_bit_identical(tmp_path, grad):
+    inp = make_inputs("C0", n_tau=2)
+    a = _chain(inp, want_grad=grad)
+    a.burn_in(100)
+    a.run(240, block=100)
+    b = _chain(inp, want_grad=grad)
+    b.burn_in(100)
+    b.run(120, block=100)
+    path = str(tmp_path / "chain.npz")
+    b.save(path)
+    from paper_2203_05632_amd import Chain, Context
+    c = Chain.load(Context.from_inputs(inp, want_grad=grad), path, want_grad=grad)
+    c.run(120, block=100)
+    assert np.array_equal(a.series(), c.series())
+    assert np.array_equal(a.walkers.cpu().numpy(), c.walkers.cpu().numpy())
+    ra, rc = a.result(), c.result()
+    assert np.array_equal(ra.mean, rc.mean)
+    if grad:
+        assert np.array_equal(ra.grad_eps, rc.grad_eps) and np.array_equal(ra.grad_coeffs, rc.grad_coeffs)
+
+
+def test_chains_on_concurrent_streams_match_sequential_runs():
+    from paper_2203_05632_amd import merge
+    inp = make_inputs("C0", n_tau=2)
+    seq = []
+    for c in range(3):
+        ch = _chain(inp, key=(5, c))
+        ch.burn_in(50)
+        ch.run(150, block=50)
+        seq.append(ch)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    par = [_chain(inp, key=(5, c), stream=streams[c]) for c in range(3)]
+    for ch in par:
+        ch.burn_in(50)
+    for _ in range(3):          # interleave the chains' launches block by block
+        for ch in par:
+            ch.run(50, block=50)
+    torch.cuda.synchronize()
+    for s, p in zip(seq, par):
+        assert np.array_equal(s.series(), p.series())
+    m = merge([ch.result() for ch in par])
+    assert m.steps == 450
+    assert np.allclose(m.mean, np.mean([ch.result().mean for ch in par], axis=0))
