@@ -40,7 +40,10 @@ def _ctx(inp, **kw):
                                              ("C1", dict(), [0.2, 0.9]),
                                              # 273 (tau, 16-walker tile pair) items: the BF16 / FP16 modes take
                                              # the 128x128-tile kernel; m = 200 leaves a half-filled last tile
-                                             ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0])])
+                                             ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0]),
+                                             # one tau per step: 276 tile pairs of 16 walkers (m = 360, a
+                                             # half-filled last tile) still take the 128x128-tile kernel
+                                             ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4])])
 def test_low_precision_step_near_oracle(prec, name, over, taus):
     inp = make_inputs(name, **over)
     wk = initial_walkers(inp)
@@ -116,7 +119,8 @@ def test_systematic_error_below_one_percent_of_sigma_precision_workload(chain_ru
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("name,over,taus", [("C1", dict(), [0.3, 1.0]),
                                              ("C0", dict(m=13, n_occ=6, n_vir=10, n_tau=3), [0.2, 0.7, 2.5]),
-                                             ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0])])
+                                             ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0]),
+                                             ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4])])
 def test_low_precision_gradients_near_fp64(prec, name, over, taus):
     """FP32 mode keeps an FP64 adjoint GEMM; BF16 and FP16 modes run the
     adjoint GEMM on BF16 operands (adjoint blocks and psi S_t)."""
@@ -136,3 +140,29 @@ def test_low_precision_gradients_near_fp64(prec, name, over, taus):
         err = np.max(np.abs(a - b)) / np.max(np.abs(b))
         print(f"{prec} {name} {over}: gradient max-norm relative deviation {err:.3e}", flush=True)
         assert err < (1e-5 if prec == "fp32" else 0.01)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_set_coefficients_refreshes_low_precision_operands(prec):
+    """After mcmp2_set_coefficients the step equals, bit for bit, the step of
+    a context built with the new coefficients (the split BF16 coefficient
+    copy of the BF16 / FP16 modes is rebuilt on the context's stream)."""
+    inp = make_inputs("C1", n_tau=2)
+    wk = dev(initial_walkers(inp))
+    taus = dev([0.3, 1.1])
+    rng = np.random.default_rng(11)
+    C2 = inp.coeffs * (1.0 + 0.05 * rng.standard_normal(inp.coeffs.shape))
+    eps2 = inp.eps.copy()
+    eps2[0] -= 0.01   # the lowest occupied energy: lambda (HOMO-LUMO gap) unchanged
+    a = _ctx(inp, precision=prec)
+    a.set_coefficients(torch.tensor(C2, device="cuda"), torch.tensor(eps2, device="cuda"))
+    ea = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    a.step(wk, taus, ea)
+    from paper_2203_05632_amd import Context
+    b = Context(inp.nuc_xyz, inp.wfn, inp.n_L, inp.n_S, inp.prim_xyz, inp.prim_exp, inp.prim_lxyz, inp.prim_norm,
+                C2, eps2, inp.n_occ, inp.n_vir, inp.m, 2, precision=prec)
+    assert b.lam == a.lam   # lambda is frozen at init; this change of energies leaves it unchanged
+    eb = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    b.step(wk, taus, eb)
+    torch.cuda.synchronize()
+    assert np.array_equal(ea.cpu().numpy(), eb.cpu().numpy())
