@@ -24,7 +24,11 @@ constexpr int GKC = 16;  // rows y of H (and of psi) per LDS chunk
 // grid: (column tiles of 32 spinors: occupied tiles first, then virtual;
 //        R / 32 row tiles).  4 waves: 16x16 output sub-tiles (wx, wk).
 // Psibar[k][x] = sum_t s_t[k] sum_y H_t[x][y] psi[k][y]; the partial
-// epsbar of this row tile goes to eps_part[row tile][k].
+// epsbar of this row tile goes to eps_part[row tile][k].  The complex
+// products take three real MFMA products (3M / Gauss form): for
+// H = a + ib and s psi = c + id,
+//   T1 = sum a c,  T2 = sum b d,  T3 = sum (a + b)(c + d),
+//   Re = T1 - T2,  Im = T3 - T1 - T2.
 __device__ inline double2 to_d2(const double2 &v) { return v; }
 __device__ inline double2 to_d2(const float2 &v) { return double2{(double)v.x, (double)v.y}; }
 
@@ -81,8 +85,8 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
         }
     };
 
-    d4v re[NT], im[NT];
-    for (int t = 0; t < NT; ++t) re[t] = im[t] = d4v{0.0, 0.0, 0.0, 0.0};
+    d4v t1[NT], t2[NT], t3[NT];
+    for (int t = 0; t < NT; ++t) t1[t] = t2[t] = t3[t] = d4v{0.0, 0.0, 0.0, 0.0};
     const int n_chunks = R / GKC;
     gload(0);
     lstore(0);
@@ -92,14 +96,13 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
         if (c + 1 < n_chunks) gload((c + 1) * GKC);
         for (int ks = 0; ks < GKC; ks += 4) {
             const double2 bv = pb[buf][ks + lk][16 * wk + li];
+            const double bs = bv.x + bv.y;
             for (int t = 0; t < NT; ++t) {
                 const double2 av = pa[buf][t][ks + lk][16 * wx + li];
-                const double c_ = bv.x * s[t], d_ = bv.y * s[t];
-                // (a + ib)(c + id) = (ac - bd) + i(ad + bc)
-                re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, c_, re[t], 0, 0, 0);
-                im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, d_, im[t], 0, 0, 0);
-                re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, d_, re[t], 0, 0, 0);
-                im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, c_, im[t], 0, 0, 0);
+                const double c_ = bv.x * s[t], d_ = bv.y * s[t], cd = bs * s[t];
+                t1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, c_, t1[t], 0, 0, 0);
+                t2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, d_, t2[t], 0, 0, 0);
+                t3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x + av.y, cd, t3[t], 0, 0, 0);
             }
         }
         if (c + 1 < n_chunks) lstore(buf ^ 1);
@@ -110,15 +113,17 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
     double e_acc = 0.0;
     for (int v = 0; v < 4; ++v) {
         const int x = x0 + 16 * wx + 4 * v + lk;
-        double yr = 0.0, yi = 0.0;
+        double yr = 0.0, yi = 0.0, re[NT], im[NT];
         for (int t = 0; t < NT; ++t) {
-            yr += re[t][v];
-            yi += im[t][v];
+            re[t] = t1[t][v] - t2[t][v];
+            im[t] = (t3[t][v] - t1[t][v]) - t2[t][v];
+            yr += re[t];
+            yi += im[t];
         }
         if (k_ok) {
             const double2 ph = to_d2(psi[(size_t)kl * R + x]);
             for (int t = 0; t < NT; ++t)  // Re(conj(psi) Y_t) weighted by +-tau_t / 2
-                e_acc += 0.5 * sign * tau[t0 + t] * (ph.x * re[t][v] + ph.y * im[t][v]);
+                e_acc += 0.5 * sign * tau[t0 + t] * (ph.x * re[t] + ph.y * im[t]);
             double2 *o = psibar + (size_t)kl * R + x;
             if (accumulate) {
                 const double2 old = *o;
@@ -146,6 +151,7 @@ __global__ void eps_reduce_kernel(const double *__restrict__ eps_part, int n_row
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsp) return;
     double acc = 0.0;
+#pragma unroll 8  // loads of 8 row tiles in flight together; the adds keep their order
     for (int r = 0; r < n_rowtiles; ++r) acc += eps_part[(size_t)r * nsp + k];
     grad_eps[k] = acc;
 }

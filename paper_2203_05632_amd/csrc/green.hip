@@ -8,10 +8,15 @@
 // Only the 8x8 blocks of walker pairs p < q enter the estimator, and
 // G(y, x) = G(x, y)^dagger, so the kernel walks the upper triangle of
 // 32x32-row block tiles (4 walker pairs per side).  A workgroup owns one block
-// tile and computes G- and G+ for up to four tau samples from a single pass
-// over the operands, on FP64 MFMA with complex numbers as real pairs: with
-// psi_x = a + ib and psi_y = c + id,
-//   Re G += a c + b d,   Im G += b c - a d.
+// tile and computes G- and G+ for up to two tau samples from a single pass
+// over the operands, on FP64 MFMA with complex numbers as real pairs.  With
+// psi_x = a + ib and psi_y = c + id the entry is Re G = sum a c + b d,
+// Im G = sum b c - a d; the kernel forms it from three real products instead
+// of four (the 3M / Gauss form of complex multiplication):
+//   T1 = sum a c,  T2 = sum b d,  T3 = sum (a + b)(c - d),
+//   Re G = T1 + T2,  Im G = T3 - T1 + T2,
+// which cuts the MFMA work by a quarter; the rounding error of Im G stays of
+// the order of the unit roundoff times |a||c| + |b||d| summed over k.
 // The tile never leaves the chip: per tau each wave stages its 16x16 G- and
 // G+ sub-tiles in LDS and contracts the (up to) four walker pairs they cover,
 //   D = Tr[G-(3,1) G+(1,3)] Tr[G-(4,2) G+(2,4)],
@@ -48,15 +53,29 @@ __device__ inline void neumaier_add(double &s, double &c, double x) {
 // Compensated sum over the n_slots partials of tau t by one block of 256
 // threads: per-thread sums over a fixed stride, then a fixed-shape tree
 // (wave shuffles, then the 4 wave totals in order) -- the same order in every
-// launch runs it, so the result is bitwise reproducible.
+// launch runs it, so the result is bitwise reproducible.  A thread's terms
+// are fetched RB at a time before they are added, so their loads overlap
+// instead of each waiting for the previous add; a term past the end reads as
+// 0.0, which leaves the sum and its compensation unchanged.
 __device__ inline void reduce_tau(const double *__restrict__ partial, int n_slots, int t, double inv_pairs,
                                   double *__restrict__ e2_out, double (*sh)[4]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    constexpr int RB = 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double *src = partial + (size_t)t * n_slots * 2;
+    const d2 *src = reinterpret_cast<const d2 *>(partial) + (size_t)t * n_slots;
     double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
-    for (int i = threadIdx.x; i < n_slots; i += 256) {
-        neumaier_add(s0, c0, src[2 * i]);
-        neumaier_add(s1, c1, src[2 * i + 1]);
+    for (int i0 = threadIdx.x; i0 < n_slots; i0 += 256 * RB) {
+        d2 v[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int i = i0 + 256 * u;
+            v[u] = i < n_slots ? src[i] : d2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            neumaier_add(s0, c0, v[u].x);
+            neumaier_add(s1, c1, v[u].y);
+        }
     }
     for (int off = 32; off >= 1; off >>= 1) {
         const double s0o = __shfl_down(s0, off, 64), c0o = __shfl_down(c0, off, 64);
@@ -98,19 +117,22 @@ __device__ inline void reduce_tau(const double *__restrict__ partial, int n_slot
 // 32 rows of the Q range, both [k][row] with the row fastest.
 constexpr int KC = 16;
 
+// One K-step of 4 spinors: the three real products T1, T2, T3 of the 3M form
+// (x = P-range operand, scaled per tau; y = Q-range operand).
 template <int NT>
 __device__ inline void mfma_kstep(const double2 *__restrict__ pa, const double2 *__restrict__ pb,
-                                  const double (&s)[NT], d4v (&acc_re)[NT], d4v (&acc_im)[NT]) {
+                                  const double (&s)[NT], d4v (&t1)[NT], d4v (&t2)[NT], d4v (&t3)[NT]) {
     const double2 x = *pa, y = *pb;
-    double a[NT], b[NT];
+    const double xs = x.x + x.y, yd = y.x - y.y;
+    double a[NT], b[NT], ab[NT];
     for (int t = 0; t < NT; ++t) {
         a[t] = x.x * s[t];
         b[t] = x.y * s[t];
+        ab[t] = xs * s[t];
     }
-    for (int t = 0; t < NT; ++t) acc_re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], y.x, acc_re[t], 0, 0, 0);
-    for (int t = 0; t < NT; ++t) acc_im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t], y.x, acc_im[t], 0, 0, 0);
-    for (int t = 0; t < NT; ++t) acc_re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t], y.y, acc_re[t], 0, 0, 0);
-    for (int t = 0; t < NT; ++t) acc_im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[t], y.y, acc_im[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) t1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], y.x, t1[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) t2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t], y.y, t2[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) t3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab[t], yd, t3[t], 0, 0, 0);
 }
 
 __device__ inline void chunk_load(const double2 *__restrict__ psi, int R, int rp, int rq, int kc, int k_hi, int e0,
@@ -144,7 +166,7 @@ __device__ inline double scale_load(const double *__restrict__ sc, int nsp, int 
 template <int NT>
 __device__ inline void stream_k(const double2 *__restrict__ psi, const double *__restrict__ sc, int nsp, int R,
                                 int rp, int rq, int k_lo, int k_hi, double2 (*panel)[2][KC][32],
-                                double (*spanel)[4 * KC], d4v (&acc_re)[NT], d4v (&acc_im)[NT]) {
+                                double (*spanel)[4 * KC], d4v (&t1)[NT], d4v (&t2)[NT], d4v (&t3)[NT]) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wp = wave >> 1, wq = wave & 1;
@@ -175,8 +197,8 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
         for (int ks = 0; ks < KC; ks += 4) {
             double s[NT];
             for (int t = 0; t < NT; ++t) s[t] = spanel[buf][t * KC + ks + lk];
-            mfma_kstep<NT>(&panel[buf][0][ks + lk][16 * wp + li], &panel[buf][1][ks + lk][16 * wq + li], s, acc_re,
-                           acc_im);
+            mfma_kstep<NT>(&panel[buf][0][ks + lk][16 * wp + li], &panel[buf][1][ks + lk][16 * wq + li], s, t1, t2,
+                           t3);
         }
         if (c + 1 < n_chunks) {
             chunk_store(panel[buf ^ 1], e0, e1, ra0, ra1, rb0, rb1);
@@ -192,7 +214,7 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
 // matrices H- and H+ (gradient of the step value with respect to the entries
 // of G- and G+, folded as Gbar + Gbar^H) into Hm / Hp [n_tau][R][R] complex.
 template <int NT, bool GRAD>
-__global__ __launch_bounds__(256) void green_contract_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD ? 4 : 2))) void green_contract_kernel(
     const double *__restrict__ psi_, const double *__restrict__ scale, const double *__restrict__ wtau,
     const double *__restrict__ hinv, const int *__restrict__ tiles, const int *__restrict__ work, int n_slots, int R,
     int no, int nsp, int m, double *__restrict__ partial, double2 *__restrict__ Hm, double2 *__restrict__ Hp,
@@ -219,11 +241,21 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
     const int rp = 32 * PT, rq = 32 * QT;
     const double *sc = scale + (size_t)t0 * nsp;
 
-    d4v gm_re[NT], gm_im[NT], gp_re[NT], gp_im[NT];
-    for (int t = 0; t < NT; ++t) gm_re[t] = gm_im[t] = gp_re[t] = gp_im[t] = d4v{0.0, 0.0, 0.0, 0.0};
-    // occupied spinors -> G-, then virtual spinors -> G+
-    stream_k<NT>(psi, sc, nsp, R, rp, rq, 0, no, panel, spanel, gm_re, gm_im);
-    stream_k<NT>(psi, sc, nsp, R, rp, rq, no, nsp, panel, spanel, gp_re, gp_im);
+    // occupied spinors -> G-, then virtual spinors -> G+ (T1, T2, T3 of the
+    // 3M form; G- is assembled before the G+ pass to free its registers)
+    d4v gm_re[NT], gm_im[NT];
+    {
+        d4v m1[NT], m2[NT], m3[NT];
+        for (int t = 0; t < NT; ++t) m1[t] = m2[t] = m3[t] = d4v{0.0, 0.0, 0.0, 0.0};
+        stream_k<NT>(psi, sc, nsp, R, rp, rq, 0, no, panel, spanel, m1, m2, m3);
+        for (int t = 0; t < NT; ++t) {
+            gm_re[t] = m1[t] + m2[t];
+            gm_im[t] = (m3[t] - m1[t]) + m2[t];
+        }
+    }
+    d4v p1[NT], p2[NT], p3[NT];
+    for (int t = 0; t < NT; ++t) p1[t] = p2[t] = p3[t] = d4v{0.0, 0.0, 0.0, 0.0};
+    stream_k<NT>(psi, sc, nsp, R, rp, rq, no, nsp, panel, spanel, p1, p2, p3);
 
     // epilogue: per tau, stage the wave's G- and G+ sub-tiles in LDS and contract
     cplx *Gm = reinterpret_cast<cplx *>(&panel[0][0][0][0]) + wave * 512;
@@ -234,7 +266,7 @@ __global__ __launch_bounds__(256) void green_contract_kernel(
         for (int v = 0; v < 4; ++v) {
             const int i = 4 * v + lk;  // MFMA f64 result row of element v
             Gm[i * 16 + li] = {gm_re[t][v], gm_im[t][v]};
-            Gp[i * 16 + li] = {gp_re[t][v], gp_im[t][v]};
+            Gp[i * 16 + li] = {p1[t][v] + p2[t][v], (p3[t][v] - p1[t][v]) + p2[t][v]};
         }
         __syncthreads();
         contract_pairs<GRAD, double2>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
@@ -295,13 +327,17 @@ void build_green_work(int T, double tile_bytes, std::vector<int> &work) {
 // Tau samples per block: NT divides n_tau (every block of the launch has NT
 // samples), and the launch's makespan is modelled as (blocks per CU, rounded
 // up) x NT.  Larger NT shares each operand panel across more samples, so the
-// largest NT within 5% of the best makespan is taken.
+// largest NT within 5% of the best makespan is taken.  NT is at most 2: with
+// three accumulator tiles per sample and function, NT = 4 leaves one wave per
+// SIMD and was measured slower than NT = 2 on the 512-pair workload.
+constexpr int kMaxTauChunk = 2;
+
 int green_tau_chunk(int nblocks, int n_tau, int n_cu) {
     auto cost = [&](int nt) { return (double)((nblocks * (n_tau / nt) + n_cu - 1) / n_cu) * nt; };
     double best = 1e300;
-    for (int nt = 1; nt <= 4; ++nt)
+    for (int nt = 1; nt <= kMaxTauChunk; ++nt)
         if (n_tau % nt == 0) best = std::min(best, cost(nt));
-    for (int nt = 4; nt >= 1; --nt)
+    for (int nt = kMaxTauChunk; nt >= 1; --nt)
         if (n_tau % nt == 0 && cost(nt) <= 1.05 * best) return nt;
     return 1;
 }
@@ -323,11 +359,10 @@ hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
                                                                        c->tiles, c->work, c->n_slots, c->R,      \
                                                                        c->no, c->nsp, c->m, c->partial, nullptr, \
                                                                        nullptr, 0.0)
-    switch (nt) {
-        case 1: LAUNCH(1); break;
-        case 2: LAUNCH(2); break;
-        case 3: LAUNCH(3); break;
-        default: LAUNCH(4); break;
+    if (nt == 1) {
+        LAUNCH(1);
+    } else {
+        LAUNCH(2);
     }
 #undef LAUNCH
     return hipGetLastError();

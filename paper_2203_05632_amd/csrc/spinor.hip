@@ -117,7 +117,10 @@ __global__ __launch_bounds__(256) void spinor_gemm_kernel(const double *__restri
     // K-steps of this wave: mu groups mu_lo + 4 wave + 16 j.  They are
     // fetched in batches of BK into registers; batch b + 1 is requested before
     // the MFMAs of batch b are issued, so its loads overlap BK x 4 MFMAs.
-    constexpr int BK = 8;
+    // BK = 2 keeps the FP64 kernel at four waves per SIMD, so every block of
+    // a 128-pair launch is resident at once (measured faster than BK = 4 or 8,
+    // whose larger stages cost occupancy).
+    constexpr int BK = 2;
     struct Stage {
         double x[BK];
         double2 ca[BK], cb[BK];
