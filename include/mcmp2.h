@@ -74,18 +74,21 @@ typedef struct {
  *   n_tau_max  : largest n_tau a step will be given (>= 1).
  *   precision  : MFMA operand types of the step's GEMMs, all with FP32
  *                accumulation outside FP64 mode:
- *                  mode   spinor GEMM     Green's GEMMs  adjoint GEMM  coefficient gradient
- *                  FP64   FP64            FP64           FP64          FP64
- *                  FP32   FP32            FP32           FP64          FP64
- *                  BF16   split BF16 (*)  BF16           BF16          BF16
- *                  FP16   split BF16 (*)  FP16           BF16          BF16
+ *                  mode   spinor GEMM     Green's GEMMs  contraction  adjoint GEMM  coefficient gradient
+ *                  FP64   FP64            FP64           FP64         FP64          FP64
+ *                  FP32   FP32            FP32           FP64         FP64          FP64
+ *                  BF16   split BF16 (*)  BF16           FP32         BF16          BF16
+ *                  FP16   split BF16 (*)  FP16           FP32         BF16          BF16
  *                (*) basis values and coefficients split as hi + lo BF16
- *                parts, three products (about 16 significant bits).  The
- *                adjoint GEMM and coefficient gradient of FP16 mode use BF16
- *                for its exponent range.  exp(+-eps tau) scalings (applied as
- *                square roots to both Green's-function operands, rounded
- *                once), pair weights, the pair contraction and every sum stay
- *                in FP64.
+ *                parts, three products (about 16 significant bits), when the
+ *                GEMM has at least one 128x128 tile per two compute units;
+ *                below that, FP32 (operands rounded from FP64).  The adjoint GEMM
+ *                and coefficient gradient of FP16 mode use BF16 for its
+ *                exponent range.  The contraction column is the type of the
+ *                traces and 4x4 block products of the pair contraction.
+ *                exp(+-eps tau) scalings (applied as square roots to both
+ *                Green's-function operands, rounded once), pair weights and
+ *                every sum stay in FP64.
  *   want_grad  : non-zero to allow gradient outputs in mcmp2_step; allocates
  *                2 n_tau_max (8 m_pad)^2 complex adjoint matrices (FP64, or
  *                packed BF16 pairs in the BF16 / FP16 modes; m_pad = m

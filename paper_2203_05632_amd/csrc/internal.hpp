@@ -121,6 +121,10 @@ hipError_t launch_coef_grad(const mcmp2_ctx *c, double *grad_coeffs);
 hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau);
 hipError_t launch_coef_lp(const mcmp2_ctx *c);
 hipError_t launch_spinor_lp(const mcmp2_ctx *c);
+// true when the split-BF16 spinor GEMM has at least one 128x128 tile per two CUs
+bool spinor_lp_tiled(const mcmp2_ctx *c);
+// XT -> XTb (gradients) and, with want_xb, the split-BF16 operand Xb
+hipError_t launch_x_lp(const mcmp2_ctx *c, bool want_xb);
 hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, double *grad_coeffs);
 int adjoint_lp_row_tiles(const mcmp2_ctx *c);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);

@@ -358,7 +358,16 @@ hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const dou
     return hipGetLastError();
 }
 
+// BF16 / FP16 modes: the split-BF16 128x128-tile GEMM when it has a tile per
+// two CUs; below that it is latency-bound, and the FP32 path (FP32 MFMA on
+// operands rounded from FP64, the more accurate of the two) writes the same
+// float2 psi in less time.
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c) {
-    if (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) return launch_spinor_lp(c);
+    if (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) {
+        if (spinor_lp_tiled(c)) return launch_spinor_lp(c);
+        const hipError_t e = launch_x_lp(c, false);  // XTb of the coefficient gradient, if requested
+        if (e != hipSuccess) return e;
+        return launch_spinor_typed<float>(c);
+    }
     return c->precision == MCMP2_FP64 ? launch_spinor_typed<double>(c) : launch_spinor_typed<float>(c);
 }

@@ -138,23 +138,32 @@ __global__ __launch_bounds__(256) void coef_lp_kernel(const double2 *__restrict_
     o[2 * blk] = lo;
 }
 
-// XT (FP64 [nb][E]) -> Xb [pt][.] split as [hi | lo | hi] and, for
-// gradients, XTb [mu][pt] (row length Ep).  64 x 64 tiles through LDS;
-// grid (ceil(nb / 64), ceil(E / 64)).
+// XT (FP64 [nb][E]) -> Xb [pt][.] split as [hi | lo | hi] (when Xb is
+// given) and, for gradients, XTb [mu][pt] (row length Ep).  32 x 32 tiles
+// through LDS, four elements per thread whose loads are all issued before the
+// first store; grid (ceil(nb / 32), ceil(E / 32)).
 __global__ __launch_bounds__(256) void x_lp_kernel(const double *__restrict__ XT, int nb, int nL, int nLp, int nSp,
                                                    int E, int Ep, __bf16 *__restrict__ Xb, __bf16 *__restrict__ XTb) {
-    __shared__ double tile[64][65];
-    const int mu0 = blockIdx.x * 64, pt0 = blockIdx.y * 64, tid = threadIdx.x;
+    __shared__ double tile[32][33];
+    const int mu0 = blockIdx.x * 32, pt0 = blockIdx.y * 32, tid = threadIdx.x;
     const int ldx = 3 * (nLp + nSp);
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int r = e >> 6, p = e & 63, mu = mu0 + r, pt = pt0 + p;
-        const double v = (mu < nb && pt < E) ? XT[(size_t)mu * E + pt] : 0.0;
-        tile[r][p] = v;
-        if (XTb && mu < nb && pt < E) XTb[(size_t)mu * Ep + pt] = (__bf16)(float)v;
+    double v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = tid + 256 * j, mu = mu0 + (e >> 5), pt = pt0 + (e & 31);
+        v[j] = (mu < nb && pt < E) ? XT[(size_t)mu * E + pt] : 0.0;
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = tid + 256 * j, r = e >> 5, p = e & 31, mu = mu0 + r, pt = pt0 + p;
+        tile[r][p] = v[j];
+        if (XTb && mu < nb && pt < E) XTb[(size_t)mu * Ep + pt] = (__bf16)(float)v[j];
+    }
+    if (!Xb) return;  // uniform over the block
     __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int p = e >> 6, r = e & 63, mu = mu0 + r, pt = pt0 + p;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = tid + 256 * j, p = e >> 5, r = e & 31, mu = mu0 + r, pt = pt0 + p;
         if (mu < nb && pt < E) {
             __bf16 hi, lo;
             split_bf16(tile[r][p], hi, lo);
@@ -258,11 +267,25 @@ hipError_t launch_coef_lp(const mcmp2_ctx *c) {
     return hipGetLastError();
 }
 
-hipError_t launch_spinor_lp(const mcmp2_ctx *c) {
-    dim3 g((c->nb + 63) / 64, (c->E + 63) / 64);
+// Measured on both sides of the threshold (conversion of the basis values
+// included): 44 tiles (340 spinors, 256 points) took 34 us against 16 us on
+// the FP32 path; 248 tiles (980 spinors, 512 points) took 68 us against 173 us.
+bool spinor_lp_tiled(const mcmp2_ctx *c) {
+    const int n_rt = (4 * c->nsp + LBM - 1) / LBM, n_ct = (c->E + LBM - 1) / LBM;
+    return 2 * 2 * n_rt * n_ct >= c->n_cu;
+}
+
+hipError_t launch_x_lp(const mcmp2_ctx *c, bool want_xb) {
+    if (!want_xb && !c->XTb) return hipSuccess;
+    dim3 g((c->nb + 31) / 32, (c->E + 31) / 32);
     x_lp_kernel<<<g, 256, 0, c->stream>>>(c->XT, c->nb, c->nL, c->nLp, c->nbp - c->nLp, c->E, c->Ep,
-                                          reinterpret_cast<__bf16 *>(c->Xb), reinterpret_cast<__bf16 *>(c->XTb));
-    hipError_t e = hipGetLastError();
+                                          want_xb ? reinterpret_cast<__bf16 *>(c->Xb) : nullptr,
+                                          reinterpret_cast<__bf16 *>(c->XTb));
+    return hipGetLastError();
+}
+
+hipError_t launch_spinor_lp(const mcmp2_ctx *c) {
+    hipError_t e = launch_x_lp(c, true);
     if (e != hipSuccess) return e;
     const int n_rt = (4 * c->nsp + LBM - 1) / LBM, n_ct = (c->E + LBM - 1) / LBM;
     const int n_items = 2 * n_rt * n_ct;

@@ -1,11 +1,13 @@
 """Low-precision operand modes (FP32, BF16, FP16 MFMA operands, FP32
-accumulation; scalings, weights, contractions and sums in FP64).
+accumulation; scalings, weights and sums in FP64, the pair contraction in
+FP64 (FP32 mode) or FP32 (BF16 / FP16 modes)).
 
 * Per step at fixed walkers and tau: deviation from the FP64 oracle, measured
   on the scale of the pair terms (mean |pair term|), within a bound set by the
   operand precision.  In the BF16 / FP16 modes every Green's-function operand
   (spinor value times sqrt(exp(+-eps tau))) is rounded once to the operand
-  type (the split-BF16 spinor GEMM adds about 2^-16), and a pair term has
+  type (the spinor GEMM -- split BF16 when it has a 128x128 tile per CU, FP32
+  below that -- adds at most about 2^-16), and a pair term has
   degree 8 in the spinor values: bound 8 u for unit roundoff u = 2^-8 (BF16),
   2^-11 (FP16).  FP32 mode: bound 1e-6 (about 17 u).
 * Over a chain (1000 steps of the 340-spinor workload and of the 980-spinor
@@ -43,7 +45,11 @@ def _ctx(inp, **kw):
                                              ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0]),
                                              # one tau per step: 276 tile pairs of 16 walkers (m = 360, a
                                              # half-filled last tile) still take the 128x128-tile kernel
-                                             ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4])])
+                                             ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4]),
+                                             # 1440 points: the split-BF16 spinor GEMM has 2 x 11 x 12 = 264
+                                             # 128x128 tiles (>= one per two CUs) and runs; at the sizes
+                                             # above the BF16 / FP16 modes take the FP32 spinor kernel
+                                             ("C1", dict(m=720, n_tau=1), [0.5])])
 def test_low_precision_step_near_oracle(prec, name, over, taus):
     inp = make_inputs(name, **over)
     wk = initial_walkers(inp)
@@ -120,7 +126,8 @@ def test_systematic_error_below_one_percent_of_sigma_precision_workload(chain_ru
 @pytest.mark.parametrize("name,over,taus", [("C1", dict(), [0.3, 1.0]),
                                              ("C0", dict(m=13, n_occ=6, n_vir=10, n_tau=3), [0.2, 0.7, 2.5]),
                                              ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0]),
-                                             ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4])])
+                                             ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4]),
+                                             ("C1", dict(m=720, n_tau=1), [0.5])])
 def test_low_precision_gradients_near_fp64(prec, name, over, taus):
     """FP32 mode keeps an FP64 adjoint GEMM; BF16 and FP16 modes run the
     adjoint GEMM on BF16 operands (adjoint blocks and psi S_t)."""
