@@ -203,8 +203,10 @@ template <typename T, int NT, bool GRAD, typename HT>
 __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, int Ko, int Ktot,
                                                        const double *__restrict__ wtau, const double *__restrict__ hinv,
                                                        const int *__restrict__ tiles, const int *__restrict__ work,
-                                                       int n_slots, int R, int m, int t0, double *__restrict__ partial,
-                                                       HT *__restrict__ Hm, HT *__restrict__ Hp, double cgrad) {
+                                                       int n_slots, int R, int m, int t_base,
+                                                       double *__restrict__ partial, HT *__restrict__ Hm,
+                                                       HT *__restrict__ Hp, double cgrad) {
+    const int t0 = t_base + (int)blockIdx.y * NT;  // tau samples t0 .. t0 + NT - 1
     constexpr int PANEL_BYTES = 2 * NT * 2 * 32 * lrow<T>() * (int)sizeof(T);
     constexpr int EPI_BYTES = 4 * 512 * (int)sizeof(cplx);
     __shared__ __align__(16) unsigned char smem[PANEL_BYTES > EPI_BYTES ? PANEL_BYTES : EPI_BYTES];
@@ -437,28 +439,42 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     using HT = std::conditional_t<sizeof(T) == 4, double2, uint32_t>;
     HT *Hm = reinterpret_cast<HT *>(c->Hm), *Hp = reinterpret_cast<HT *>(c->Hp);
     const int nblocks = c->n_slots / 4;
-    constexpr int NTMAX = sizeof(T) == 4 ? 2 : 4;  // FP32 panels are twice as large
-    for (int t0 = 0; t0 < n_tau; t0 += NTMAX) {
-        const int nt = std::min(NTMAX, n_tau - t0);
-#define LP_LAUNCH(NTV)                                                                                            \
-    if (grad)                                                                                                     \
-        green_lp_kernel<T, NTV, true, HT><<<nblocks, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,       \
-                                                                      c->tiles, c->work, c->n_slots, c->R, c->m, \
-                                                                      t0, c->partial, Hm, Hp, cgrad);            \
-    else                                                                                                          \
-        green_lp_kernel<T, NTV, false, HT><<<nblocks, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,      \
-                                                                       c->tiles, c->work, c->n_slots, c->R,      \
-                                                                       c->m, t0, c->partial, nullptr, nullptr,   \
-                                                                       0.0)
-        switch (nt) {
-            case 1: LP_LAUNCH(1); break;
-            case 2: LP_LAUNCH(2); break;
-            case 3: LP_LAUNCH(3); break;
-            default: LP_LAUNCH(4); break;
+#define LP_LAUNCH(NTV)                                                                                           \
+    if (grad)                                                                                                    \
+        green_lp_kernel<T, NTV, true, HT><<<grid, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,         \
+                                                                   c->tiles, c->work, c->n_slots, c->R, c->m,   \
+                                                                   t0, c->partial, Hm, Hp, cgrad);              \
+    else                                                                                                         \
+        green_lp_kernel<T, NTV, false, HT><<<grid, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,        \
+                                                                    c->tiles, c->work, c->n_slots, c->R, c->m,  \
+                                                                    t0, c->partial, nullptr, nullptr, 0.0)
+    if constexpr (sizeof(T) == 4) {
+        // FP32: one launch, tau chunks in the grid's second dimension, NT
+        // (at most 2: FP32 panels are twice as large) from the same makespan
+        // model as the FP64 kernel
+        const int nt = green_tau_chunk(nblocks, n_tau, c->n_cu), t0 = 0;
+        const dim3 grid(nblocks, n_tau / nt);
+        if (nt == 1) {
+            LP_LAUNCH(1);
+        } else {
+            LP_LAUNCH(2);
         }
+        return hipGetLastError();
+    } else {
+        constexpr int NTMAX = 4;
+        const dim3 grid(nblocks);
+        for (int t0 = 0; t0 < n_tau; t0 += NTMAX) {
+            const int nt = std::min(NTMAX, n_tau - t0);
+            switch (nt) {
+                case 1: LP_LAUNCH(1); break;
+                case 2: LP_LAUNCH(2); break;
+                case 3: LP_LAUNCH(3); break;
+                default: LP_LAUNCH(4); break;
+            }
 #undef LP_LAUNCH
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }

@@ -111,6 +111,9 @@ hipError_t launch_advance(const mcmp2_ctx *c, double *walkers, double *w, uint64
 hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau);
 hipError_t launch_spinor_gemm(const mcmp2_ctx *c);
 hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad);
+// Tau samples per block (1 or 2, dividing n_tau) of the 32x32-tile FP64 and
+// FP32 Green's kernels for a launch of nblocks tile pairs (makespan model).
+int green_tau_chunk(int nblocks, int n_tau, int n_cu);
 hipError_t launch_green_lp(const mcmp2_ctx *c, int n_tau, bool grad);
 // BF16 / FP16: 128 x 128 block tiles (16 walkers a side) when they fill the GPU
 bool green_big_selected(const mcmp2_ctx *c, int n_tau);
