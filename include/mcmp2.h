@@ -52,6 +52,8 @@ enum {
 /* Operand precision of the spinor and Green's-function contractions.
  * Exponential scalings, weights and all accumulations stay in FP64. */
 enum { MCMP2_FP64 = 0, MCMP2_FP32 = 1, MCMP2_BF16 = 2, MCMP2_FP16 = 3 };
+/* electron-electron interaction of the integrand (mcmp2_set_interaction) */
+enum { MCMP2_COULOMB = 0, MCMP2_GAUNT = 1, MCMP2_BREIT = 2 };
 
 /* Molecule, weight function and basis (host memory, caller-owned, copied by init). */
 typedef struct {
@@ -119,7 +121,8 @@ int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps
  *   Gradients overwrite their outputs.  Either requires want_grad at init
  *   (ESTATE otherwise); they come from a hand-written adjoint of the same
  *   step (Green's-function blocks recomputed, not stored between calls).
- * Errors: EINVAL (null pointers, n_tau out of range), ESTATE, EDEVICE.
+ * Errors: EINVAL (null pointers, n_tau out of range, gradient outputs with a
+ * non-Coulomb interaction), ESTATE, EDEVICE.
  */
 int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
                double *grad_eps, double *grad_coeffs);
@@ -133,6 +136,29 @@ int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t
  * Errors: EINVAL (null context), EDEVICE.
  */
 int mcmp2_set_coefficients(mcmp2_ctx *ctx, const double *coeffs, const double *eps);
+
+/*
+ * mcmp2_set_interaction -- choose the electron-electron interaction of the
+ * integrand for the following steps.  Sec. II of the paper gives the operator
+ *   g(1,2) = 1/r12 - alpha(1).alpha(2) / (2 r12)
+ *            - (alpha(1).r12)(alpha(2).r12) / (2 r12^3)
+ * (alpha: the Dirac matrices of Eq. alpha acting on each electron's four
+ * components) and keeps only its first, Coulomb term, which is the default:
+ *   MCMP2_COULOMB  1/r12 (the paper's runs)
+ *   MCMP2_GAUNT    1/r12 - alpha(1).alpha(2) / (2 r12)
+ *   MCMP2_BREIT    the full operator above.
+ * With alpha inserted, the direct and exchange traces of the integrand carry
+ * a Dirac matrix next to every Green's-function factor at the point it acts
+ * on, weighted per walker pair by the 4x4 coefficients of g in the basis
+ * (1, alpha_x, alpha_y, alpha_z) x (1, alpha_x, alpha_y, alpha_z).
+ * The step's outputs keep their meaning (direct, exchange, total of the
+ * estimator).  The Gaunt and Breit terms are evaluated in FP64 mode only and
+ * without gradient outputs.
+ * Errors: EINVAL (null context, unknown kind, Gaunt / Breit outside FP64
+ * mode).  mcmp2_step returns EINVAL when gradient outputs are requested with
+ * a non-Coulomb interaction.
+ */
+int mcmp2_set_interaction(mcmp2_ctx *ctx, int32_t interaction);
 
 /*
  * mcmp2_pair_weights -- w(r1p, r2p) = g(r1p) g(r2p) / (N_g r12p) for every

@@ -13,9 +13,10 @@ LIB_PATH = os.path.join(HERE, "libmcmp2.so")
 
 MCMP2_OK, MCMP2_EINVAL, MCMP2_ENOMEM, MCMP2_EDEVICE, MCMP2_ESTATE = 0, -1, -2, -3, -4
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+INTERACTIONS = {"coulomb": 0, "gaunt": 1, "breit": 2}
 
 # Every symbol declared in include/mcmp2.h.
-EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_set_coefficients", "mcmp2_pair_weights", "mcmp2_metropolis", "mcmp2_sample_tau",
+EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_set_coefficients", "mcmp2_set_interaction", "mcmp2_pair_weights", "mcmp2_metropolis", "mcmp2_sample_tau",
            "mcmp2_advance", "mcmp2_accumulate", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_destroy",
            "mcmp2_last_error"]
 KERNELS = ["walker_weights", "step_prep", "spinor_gemm", "green_contract", "reduce", "metropolis", "sample_tau",
@@ -60,6 +61,8 @@ def load() -> ctypes.CDLL:
     lib.mcmp2_step.restype = ctypes.c_int
     lib.mcmp2_set_coefficients.argtypes = [vp, vp, vp]
     lib.mcmp2_set_coefficients.restype = ctypes.c_int
+    lib.mcmp2_set_interaction.argtypes = [vp, i32]
+    lib.mcmp2_set_interaction.restype = ctypes.c_int
     lib.mcmp2_pair_weights.argtypes = [vp, vp, vp]
     lib.mcmp2_pair_weights.restype = ctypes.c_int
     lib.mcmp2_metropolis.argtypes = [vp, vp, vp, u64, u64, u64, dbl, vp]

@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import KERNELS, PRECISIONS, Basis, check, load
+from ._lib import INTERACTIONS, KERNELS, PRECISIONS, Basis, check, load
 
 
 def _host(a, dtype):
@@ -108,6 +108,11 @@ class Context:
             self._h,
             None if coeffs is None else _dev(coeffs, (2, self.n_b, self.n_sp), torch.complex128, name="coeffs"),
             None if eps is None else _dev(eps, (self.n_sp,), name="eps")))
+
+    def set_interaction(self, kind: str) -> None:
+        """Electron-electron interaction of the following steps: "coulomb"
+        (default), "gaunt" or "breit" (FP64 contexts, no gradients)."""
+        check(self._lib.mcmp2_set_interaction(self._h, INTERACTIONS[kind]))
 
     def pair_weights(self, walkers: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
         check(self._lib.mcmp2_pair_weights(self._h, _dev(walkers, (self.m, 2, 3), name="walkers"),

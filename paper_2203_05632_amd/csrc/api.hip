@@ -37,7 +37,7 @@ int dalloc(T **p, size_t n) {
 void profiler_release(Profiler &p);
 void free_ctx(mcmp2_ctx *c) {
     profiler_release(c->prof);
-    void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->psi,
+    void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->rhat, c->psi,
                     c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT,
                     c->Hm, c->Hp, c->psibar, c->eps_part, c->U, c->Vt, c->tiles16,
                     c->Cb, c->Xb, c->XTb, c->PBb};
@@ -230,6 +230,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(dalloc(&c->coef, 2 * 2 * (size_t)nb * nsp));
     TRY(dalloc(&c->eps, (size_t)nsp));
     TRY(dalloc(&c->hinv, (size_t)c->m_pad));
+    TRY(dalloc(&c->rhat, 4 * (size_t)c->m_pad));
     TRY(dalloc(&c->psi, 2 * (size_t)nsp * c->R));  // double2 (FP64) or float2 (low precision)
     if (precision != MCMP2_FP64) {
         unsigned char *u = nullptr;
@@ -319,6 +320,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(check_hip(hipMemset(c->XT, 0, sizeof(double) * (size_t)nb * c->E), "hipMemset"));
     TRY(check_hip(hipMemset(c->psi, 0, 2 * sizeof(double) * (size_t)nsp * c->R), "hipMemset"));
     TRY(check_hip(hipMemset(c->hinv, 0, sizeof(double) * c->m_pad), "hipMemset"));
+    TRY(check_hip(hipMemset(c->rhat, 0, 4 * sizeof(double) * c->m_pad), "hipMemset"));
     TRY(check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize"));
     *out = c;
     return MCMP2_OK;
@@ -339,6 +341,10 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
         set_error("gradient outputs requested but the context was created with want_grad = 0");
         return MCMP2_ESTATE;
     }
+    if (grad && c->interaction != MCMP2_COULOMB) {
+        set_error("gradients are available for the Coulomb interaction only");
+        return MCMP2_EINVAL;
+    }
     int rc;
     if ((rc = timed(c, MCMP2_K_STEP_PREP, "step_prep", [&] { return launch_step_prep(c, walkers, tau, n_tau); })) !=
         MCMP2_OK)
@@ -356,6 +362,23 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
         return rc;
     if (!grad_coeffs) return MCMP2_OK;
     return timed(c, MCMP2_K_COEF_GRAD, "coef_grad", [&] { return launch_coef_grad(c, grad_coeffs); });
+}
+
+extern "C" int mcmp2_set_interaction(mcmp2_ctx *c, int32_t interaction) {
+    if (!c) {
+        set_error("null context");
+        return MCMP2_EINVAL;
+    }
+    if (interaction < MCMP2_COULOMB || interaction > MCMP2_BREIT) {
+        set_error("interaction %d is not one of MCMP2_COULOMB, _GAUNT, _BREIT", interaction);
+        return MCMP2_EINVAL;
+    }
+    if (interaction != MCMP2_COULOMB && c->precision != MCMP2_FP64) {
+        set_error("the Gaunt and Breit terms are available in FP64 mode only");
+        return MCMP2_EINVAL;
+    }
+    c->interaction = interaction;
+    return MCMP2_OK;
 }
 
 extern "C" int mcmp2_set_coefficients(mcmp2_ctx *c, const double *coeffs, const double *eps) {

@@ -142,6 +142,159 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
 #undef GB
 }
 
+// ---------------------------------------------------------------------------
+// Gaunt / Breit interaction (FP64).  g = sum_{mu nu} W_{mu nu}(r12) s_mu(1) s_nu(2)
+// with s_0 = 1 and s_k = alpha_k (Eq. alpha), W_00 = 1/r, W_0k = W_k0 = 0,
+// W_kl = -(delta_kl + c rhat_k rhat_l) / (2 r) (c = 1: both Breit terms of
+// Sec. II, c = 0: the Gaunt term alone).  The 1/r12 and 1/r34 factors cancel
+// against the pair weights as in the Coulomb case, leaving the dimensionless
+// B_{mu nu} = r W_{mu nu} per walker pair.  With A13 = G-(1,3), A24 = G-(2,4),
+// P_xy = G+(x,y) (G-(3,1) = A13^H, G-(4,2) = A24^H):
+//   D = sum B12[mu nu] B34[rho sig] Tr[A13^H s_mu P13 s_rho] Tr[A24^H s_nu P24 s_sig]
+//   X = sum B12[mu nu] B34[rho sig] Tr[A13^H s_mu P14 s_sig A24^H s_nu P23 s_rho]
+// (s_rho acts at point 3, s_sig at point 4).
+//
+// On the components (L alpha, L beta, S alpha, S beta) every s_mu is
+// monomial: row b holds its one non-zero entry ph(mu, b) in column
+// b ^ sx(mu); alpha_x: 1; alpha_y: -i (b even), +i (b odd); alpha_z: +1
+// (b even), -1 (b odd).  Products with s_mu are index permutations and phases.
+__device__ __forceinline__ int sx(int mu) { return mu == 0 ? 0 : (mu == 3 ? 2 : 3); }
+__device__ __forceinline__ cplx sph(int mu, int b, cplx z) {  // ph(mu, b) z
+    if (mu == 2) return (b & 1) ? cplx{-z.im, z.re} : cplx{z.im, -z.re};
+    if (mu == 3) return (b & 1) ? cplx{-z.re, -z.im} : z;
+    return z;
+}
+// B[mu][nu] of one walker pair from its unit vector u (mu, nu may be runtime values)
+__device__ __forceinline__ double bw(int mu, int nu, double ux, double uy, double uz, double c) {
+    if (mu == 0 || nu == 0) return (mu == 0 && nu == 0) ? 1.0 : 0.0;
+    const double um = mu == 1 ? ux : (mu == 2 ? uy : uz), un = nu == 1 ? ux : (nu == 2 ? uy : uz);
+    return -0.5 * ((mu == nu ? 1.0 : 0.0) + c * um * un);
+}
+
+// One walker pair (p, q) per 16 lanes, tiles as for contract_pair (FP64
+// complex); rhat [m_pad][4]: unit vectors of r1p - r2p; c: weight of the
+// second Breit term.  Returns the weighted direct and exchange terms.
+__device__ __attribute__((always_inline)) inline void contract_pair_breit(const cplx *Gm, const cplx *Gp, int ld, int p, int q, bool ok,
+                                           const double *__restrict__ hinv, const double *__restrict__ rhat,
+                                           double c, double wt, double &dir, double &exc) {
+    const int lane = threadIdx.x & 63, l16 = lane & 15, grp = lane & ~15;
+#define GB(G, e, f, i, j) G[(4 * (e) + (i)) * ld + 4 * (f) + (j)]
+    const double ux = rhat[4 * p], uy = rhat[4 * p + 1], uz = rhat[4 * p + 2];
+    const double vx = rhat[4 * q], vy = rhat[4 * q + 1], vz = rhat[4 * q + 2];
+
+    // direct: lane (mu, rho) = (l16 >> 2, l16 & 3) forms T1[mu][rho] and T2[mu][rho]
+    cplx dterm;
+    {
+        const int mu = l16 >> 2, rho = l16 & 3, xm = sx(mu), xr = sx(rho);
+        cplx t1 = {0, 0}, t2 = {0, 0};
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                // Tr[A^H s_mu P s_rho] = sum_{a,b} conj(A[b][a]) ph(mu, b) P[b ^ xm][a ^ xr] ph(rho, a ^ xr)
+                const cplx u1 = sph(mu, b, conjc(GB(Gm, 0, 0, b, a))), u2 = sph(mu, b, conjc(GB(Gm, 1, 1, b, a)));
+                const cplx v1 = sph(rho, a ^ xr, GB(Gp, 0, 0, b ^ xm, a ^ xr));
+                const cplx v2 = sph(rho, a ^ xr, GB(Gp, 1, 1, b ^ xm, a ^ xr));
+                t1 = cadd(t1, cmul(u1, v1));
+                t2 = cadd(t2, cmul(u2, v2));
+            }
+        // sum_{nu, sig} B12[mu][nu] B34[rho][sig] T2[nu][sig], T2 gathered from lane 4 nu + sig
+        cplx acc = {0, 0};
+#pragma unroll
+        for (int nu = 0; nu < 4; ++nu)
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg) {
+                const cplx t = shfl_c(t2, grp | (4 * nu + sg));
+                const double w = bw(mu, nu, ux, uy, uz, c) * bw(rho, sg, vx, vy, vz, c);
+                acc = {acc.re + w * t.re, acc.im + w * t.im};
+            }
+        dterm = cmul(t1, acc);
+    }
+
+    // exchange: lane (a, b) = (l16 >> 2, l16 & 3) forms element [a][b] of
+    //   L_{mu sig} = A13^H s_mu P14 s_sig  and element [b][a] of  R_{nu rho} = A24^H s_nu P23 s_rho,
+    //   L_{mu sig}[a][b] = ph(sig, b ^ x_sig) sum_k conj(A13[k ^ x_mu][a]) ph(mu, k ^ x_mu) P14[k][b ^ x_sig]
+    //   R_{nu rho}[b][a] = ph(rho, a ^ x_rho) sum_k conj(A24[k ^ x_nu][b]) ph(nu, k ^ x_nu) P23[k][a ^ x_rho]
+    // and sums L_{mu sig}[a][b] Rw[mu][sig] with Rw[mu][sig] = sum B12[mu][nu] B34[rho][sig] R_{nu rho}[b][a].
+    cplx xterm = {0, 0};
+    {
+        const int a = l16 >> 2, b = l16 & 3;
+        cplx S[4][4];  // S[nu][sig] = sum_rho B34[rho][sig] R_{nu rho}
+#pragma unroll
+        for (int nu = 0; nu < 4; ++nu) {
+            cplx Rr[4];
+#pragma unroll
+            for (int rho = 0; rho < 4; ++rho) {
+                const int cc = a ^ sx(rho);
+                cplx z = {0, 0};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    z = cadd(z, cmul(sph(nu, k ^ sx(nu), conjc(GB(Gm, 1, 1, k ^ sx(nu), b))), GB(Gp, 1, 0, k, cc)));
+                Rr[rho] = sph(rho, cc, z);
+            }
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg) {
+                cplx t = {0, 0};
+#pragma unroll
+                for (int rho = 0; rho < 4; ++rho) {
+                    const double w = bw(rho, sg, vx, vy, vz, c);
+                    t = {t.re + w * Rr[rho].re, t.im + w * Rr[rho].im};
+                }
+                S[nu][sg] = t;
+            }
+        }
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg) {
+                cplx rw = {0, 0};
+#pragma unroll
+                for (int nu = 0; nu < 4; ++nu) {
+                    const double w = bw(mu, nu, ux, uy, uz, c);
+                    rw = {rw.re + w * S[nu][sg].re, rw.im + w * S[nu][sg].im};
+                }
+                const int cc = b ^ sx(sg);
+                cplx y = {0, 0};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    y = cadd(y, cmul(sph(mu, k ^ sx(mu), conjc(GB(Gm, 0, 0, k ^ sx(mu), a))), GB(Gp, 0, 1, k, cc)));
+                xterm = cadd(xterm, cmul(sph(sg, cc, y), rw));
+            }
+    }
+#undef GB
+    for (int mask = 8; mask >= 1; mask >>= 1) {
+        dterm = cadd(dterm, shfl_xor_c(dterm, mask));
+        xterm = cadd(xterm, shfl_xor_c(xterm, mask));
+    }
+    dir = exc = 0.0;
+    if (ok) {
+        const double W = hinv[p] * hinv[q] / wt;
+        dir = -0.5 * dterm.re * W;
+        exc = 0.5 * xterm.re * W;
+    }
+}
+
+// contract_pairs with the Gaunt / Breit interaction (FP64, no gradients).
+__device__ __attribute__((always_inline)) inline void contract_pairs_breit(const cplx *Gm, const cplx *Gp, int PT, int QT, int m,
+                                            const double *__restrict__ hinv, const double *__restrict__ rhat,
+                                            double c, double wt, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wp = wave >> 1, wq = wave & 1;
+    const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
+    const int p = kTileWalkers * PT + 2 * wp + pp, q = kTileWalkers * QT + 2 * wq + qq;
+    double dir, exc;
+    contract_pair_breit(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv, rhat,
+                        c, wt, dir, exc);
+    const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
+                 d3 = __shfl(dir, 48, 64);
+    const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
+                 x3 = __shfl(exc, 48, 64);
+    if (lane == 0) {
+        out[0] = ((d0 + d1) + d2) + d3;
+        out[1] = ((x0 + x1) + x2) + x3;
+    }
+}
+
 // One wave, one tau sample.  Gm / Gp: this wave's 16x16 sub-tiles of G- and
 // G+ (complex FP64, row-major, rows 8 pp + 4 e + i of block-tile row PT,
 // columns 8 qq + 4 f + j of block-tile column QT; the wave's sub-tile origin

@@ -213,12 +213,15 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
 // GRAD: also write, per walker pair, the 8x8 blocks of the Hermitian adjoint
 // matrices H- and H+ (gradient of the step value with respect to the entries
 // of G- and G+, folded as Gbar + Gbar^H) into Hm / Hp [n_tau][R][R] complex.
-template <int NT, bool GRAD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD ? 4 : 2))) void green_contract_kernel(
-    const double *__restrict__ psi_, const double *__restrict__ scale, const double *__restrict__ wtau,
-    const double *__restrict__ hinv, const int *__restrict__ tiles, const int *__restrict__ work, int n_slots, int R,
-    int no, int nsp, int m, double *__restrict__ partial, double2 *__restrict__ Hm, double2 *__restrict__ Hp,
-    double cgrad) {
+// BREIT: Gaunt / Breit interaction in the contraction (no gradients; rhat
+// [m_pad][4] unit vectors of r1p - r2p, gauge = weight of the second Breit term).
+template <int NT, bool GRAD, bool BREIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD && !BREIT ? 4 : 2))) void
+green_contract_kernel(const double *__restrict__ psi_, const double *__restrict__ scale,
+                      const double *__restrict__ wtau, const double *__restrict__ hinv, const int *__restrict__ tiles,
+                      const int *__restrict__ work, int n_slots, int R, int no, int nsp, int m,
+                      double *__restrict__ partial, double2 *__restrict__ Hm, double2 *__restrict__ Hp, double cgrad,
+                      const double *__restrict__ rhat, double gauge) {
     const int t0 = (int)blockIdx.y * NT;
     // 2 buffers x (A, B) x KC x 32 complex = 32 KB; reused for the G tiles of the epilogue
     __shared__ double2 panel[2][2][KC][32];
@@ -269,10 +272,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && 
             Gp[i * 16 + li] = {p1[t][v] + p2[t][v], (p3[t][v] - p1[t][v]) + p2[t][v]};
         }
         __syncthreads();
-        contract_pairs<GRAD, double2>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
-                             partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
-                             GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
-                             GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
+        if constexpr (BREIT)
+            contract_pairs_breit(Gm, Gp, PT, QT, m, hinv, rhat, gauge, wtau[t0 + t],
+                                 partial + ((size_t)(t0 + t) * n_slots + slot) * 2);
+        else
+            contract_pairs<GRAD, double2>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
+                                          partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
+                                          GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
+                                          GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
         __syncthreads();  // the sub-tiles are rewritten for the next tau
     }
 }
@@ -347,18 +354,25 @@ hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
     const int nblocks = c->n_slots / 4;  // one work-list entry per block, four partial slots
-    const int nt = green_tau_chunk(nblocks, n_tau, c->n_cu);
+    const bool breit = c->interaction != MCMP2_COULOMB;  // mcmp2_step rejects gradients with it
+    // one tau per block with the Gaunt / Breit contraction: its epilogue
+    // needs the registers that a second tau's accumulators would hold
+    const int nt = breit ? 1 : green_tau_chunk(nblocks, n_tau, c->n_cu);
     const dim3 grid(nblocks, n_tau / nt);
-#define LAUNCH(NTV)                                                                                             \
-    if (grad)                                                                                                   \
-        green_contract_kernel<NTV, true><<<grid, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,       \
-                                                                      c->tiles, c->work, c->n_slots, c->R, c->no, \
-                                                                      c->nsp, c->m, c->partial, Hm, Hp, cgrad);   \
-    else                                                                                                        \
-        green_contract_kernel<NTV, false><<<grid, 256, 0, c->stream>>>(c->psi, c->scale, c->wtau, c->hinv,      \
-                                                                       c->tiles, c->work, c->n_slots, c->R,      \
-                                                                       c->no, c->nsp, c->m, c->partial, nullptr, \
-                                                                       nullptr, 0.0)
+    const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
+#define LAUNCH(NTV)                                                                                              \
+    if (grad)                                                                                                    \
+        green_contract_kernel<NTV, true, false><<<grid, 256, 0, c->stream>>>(                                    \
+            c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,        \
+            c->partial, Hm, Hp, cgrad, c->rhat, 0.0);                                                            \
+    else if (breit)                                                                                              \
+        green_contract_kernel<NTV, false, true><<<grid, 256, 0, c->stream>>>(                                    \
+            c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,        \
+            c->partial, nullptr, nullptr, 0.0, c->rhat, gauge);                                                  \
+    else                                                                                                         \
+        green_contract_kernel<NTV, false, false><<<grid, 256, 0, c->stream>>>(                                   \
+            c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,        \
+            c->partial, nullptr, nullptr, 0.0, c->rhat, 0.0)
     if (nt == 1) {
         LAUNCH(1);
     } else {

@@ -39,6 +39,7 @@ struct mcmp2_ctx {
     int n_tau_max = 0;
     int precision = MCMP2_FP64;
     int want_grad = 0;
+    int interaction = MCMP2_COULOMB;  // mcmp2_set_interaction
     double lambda = 0.0, Ng = 0.0;
 
     // device memory
@@ -50,6 +51,7 @@ struct mcmp2_ctx {
     double *eps = nullptr;    // [nsp]
     double *XT = nullptr;     // [nb][E] basis values, point fastest (padding points stay zero)
     double *hinv = nullptr;   // [m_pad] N_g / (g(r1p) g(r2p))
+    double *rhat = nullptr;   // [m_pad][4] unit vector of r1p - r2p (x, y, z, 0)
     double *psi = nullptr;    // [nsp][R] complex, row fastest (double2; float2 for low-precision modes)
     void *U = nullptr;        // low-precision modes: [n_tau_max][R][Ktot] scaled operands (see green_lp.hip)
     int Ko = 0, Ktot = 0;     // K extents of the occupied segment and of all spinors (reals, multiples of the K chunk)

@@ -7,7 +7,8 @@
 // Two kernels:
 //   step_prep    -- XT[mu][pt] = chi_mu(r_pt) (FP64, point index fastest),
 //                   plus the per-step scalars the Green's-function kernel
-//                   needs: N_g / (g(r1p) g(r2p)) per walker, the tau scalings
+//                   needs: N_g / (g(r1p) g(r2p)) and the unit vector of
+//                   r1p - r2p per walker, the tau scalings
 //                   exp(+eps_i tau) / exp(-eps_a tau) and w(tau);
 //   spinor_gemm  -- psi[k][4 pt + c] (complex), a real x complex GEMM on
 //                   FP64 MFMA (v_mfma_f64_16x16x4f64).
@@ -40,7 +41,8 @@ __device__ inline double basis_value(const double4 &geo, const double2 &nl, doub
 __global__ __launch_bounds__(128) void step_prep_kernel(
     const double *__restrict__ walkers, int n_pts, int E, int nb, const double4 *__restrict__ pgeo,
     const double2 *__restrict__ pnl, double *__restrict__ XT, int m, const double *__restrict__ nuc,
-    const double *__restrict__ gpar, int n_nuc, double Ng, double *__restrict__ hinv, const double *__restrict__ tau,
+    const double *__restrict__ gpar, int n_nuc, double Ng, double *__restrict__ hinv, double *__restrict__ rhat,
+    const double *__restrict__ tau,
     const double *__restrict__ eps, int n_tau, int nsp, int no, double lambda, double *__restrict__ scale,
     double *__restrict__ wtau) {
     const int mu = blockIdx.y;
@@ -58,6 +60,13 @@ __global__ __launch_bounds__(128) void step_prep_kernel(
             const double g1 = g_value(r[0], r[1], r[2], nuc, gpar, n_nuc);
             const double g2 = g_value(r[3], r[4], r[5], nuc, gpar, n_nuc);
             hinv[i] = Ng / (g1 * g2);
+            const double dx = r[0] - r[3], dy = r[1] - r[4], dz = r[2] - r[5];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double inv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;  // coincident electrons: no direction
+            rhat[4 * i] = dx * inv;
+            rhat[4 * i + 1] = dy * inv;
+            rhat[4 * i + 2] = dz * inv;
+            rhat[4 * i + 3] = 0.0;
         } else if (i < m + n_tau * nsp) {
             const int j = i - m, t = j / nsp, k = j - t * nsp;
             const double tv = tau[t];
@@ -353,7 +362,8 @@ hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const dou
     dim3 grid((n_pts + 127) / 128, c->nb + 1);
     step_prep_kernel<<<grid, 128, 0, c->stream>>>(
         walkers, n_pts, c->E, c->nb, reinterpret_cast<const double4 *>(c->pgeo),
-        reinterpret_cast<const double2 *>(c->pnl), c->XT, c->m, c->nuc, c->gpar, c->n_nuc, c->Ng, c->hinv, tau, c->eps,
+        reinterpret_cast<const double2 *>(c->pnl), c->XT, c->m, c->nuc, c->gpar, c->n_nuc, c->Ng, c->hinv, c->rhat, tau,
+        c->eps,
         n_tau, c->nsp, c->no, c->lambda, c->scale, c->wtau);
     return hipGetLastError();
 }

@@ -40,3 +40,9 @@ def test_init_rejects_bad_arguments_before_touching_device():
     out = ctypes.c_void_p()
     rc = lib.mcmp2_init(None, None, None, 1, 1, 2, 1, 0, 0, None, ctypes.byref(out))
     assert rc == -1 and b"null" in lib.mcmp2_last_error()
+
+
+def test_set_interaction_rejects_null_context():
+    from paper_2203_05632_amd import load
+    lib = load()
+    assert lib.mcmp2_set_interaction(None, 2) == -1 and b"null" in lib.mcmp2_last_error()
