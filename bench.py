@@ -35,8 +35,10 @@ sys.path.insert(0, ROOT)
 PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad", "accumulate"]
 HBM_PEAK_GBS = 8000.0   # published HBM3E bandwidth of one MI355X
 PROFILE_STEPS = 300   # steps of the HIP-event-timed pass after each throughput run
+# (operand precision, gradients[, interaction]); the interaction variants run the
+# Gaunt / Breit terms of the electron-electron operator (FP64, no gradients)
 HEADLINE_VARIANTS = [("fp32", False), ("bf16", False), ("fp16", False), ("fp64", True), ("bf16", True),
-                     ("fp16", True)]
+                     ("fp16", True), ("fp64", False, "gaunt"), ("fp64", False, "breit")]
 LARGEST_VARIANTS = [("fp64", True), ("fp32", True), ("bf16", False), ("bf16", True), ("fp16", True)]
 METRIC = "MC steps/s and var×time for E2(+grad), FP32/BF16 vs FP64, 1 MI355X"
 # published dense peaks of one MI355X (TFLOP/s) for the GEMM operand type
@@ -163,7 +165,7 @@ def cpu_baseline(inp, wk0, key, delta, seconds: float):
                       f"{el:.1f} s on the host"}
 
 
-def run_variant(inp, precision, grad, state, K, W, Kp):
+def run_variant(inp, precision, grad, state, K, W, Kp, interaction="coulomb"):
     """Replay the burned-in trajectory: W warmup steps, K timed steps, then Kp
     more steps with HIP-event timing of the GEMM kernels (recording events
     around every launch costs ~10% of a small step, so it stays out of the
@@ -173,6 +175,7 @@ def run_variant(inp, precision, grad, state, K, W, Kp):
 
     from paper_2203_05632_amd import Context
     ctx = Context.from_inputs(inp, precision=precision, want_grad=grad)
+    ctx.set_interaction(interaction)
     wk, w = state["wk"].clone(), state["w"].clone()
     key, delta, step = state["key"], state["delta"], state["step"]
     tau = torch.zeros(inp.n_tau, dtype=torch.float64, device="cuda")
@@ -434,12 +437,14 @@ def measure_workload(name, K, W, n_burn, variants, Kv=None, grad_steps=None):
                     "avg_us": round(tot_ms / n_l * 1e3, 2), "launches_per_step": n_l // Kp,
                     "flops_per_launch": flops / (n_l // Kp), "event_steps": Kp}
     out_vars = {}
-    for prec, grad in variants:
+    for var in variants:
+        prec, grad = var[0], var[1]
+        inter = var[2] if len(var) > 2 else "coulomb"
         # runs with an FP64 adjoint GEMM (FP64 and FP32 modes) are ~10x slower: fewer steps
         Kn = (grad_steps if (grad and prec in ("fp64", "fp32") and grad_steps) else (Kv or K))
         Kpn = min(Kn, PROFILE_STEPS)
-        el, vals, vprof = run_variant(inp, prec, grad, state, Kn, W, Kpn)
-        vname = prec + ("+grad" if grad else "")
+        el, vals, vprof = run_variant(inp, prec, grad, state, Kn, W, Kpn, inter)
+        vname = prec + ("+grad" if grad else "") + ("" if inter == "coulomb" else "+" + inter)
         v = {"steps": Kn, "steps_per_s": round(Kn / el, 2), "ms_per_step": round(1e3 * el / Kn, 5),
              "speedup_vs_fp64": round((Kn / el) / steps_per_s, 3)}
         if grad and "fp64+grad" in out_vars:
@@ -447,7 +452,10 @@ def measure_workload(name, K, W, n_burn, variants, Kv=None, grad_steps=None):
         v["kernels"] = kernel_table(vprof, kflops, Kpn, prec)
         if Kn == K and Kn >= 200:
             d = vals - ref_vals
-            v["systematic_over_sigma"] = float(f"{abs(d.mean()) / sbar:.3e}")
+            if inter == "coulomb":  # same estimator at lower precision: the difference is its error
+                v["systematic_over_sigma"] = float(f"{abs(d.mean()) / sbar:.3e}")
+            else:  # another estimator: the mean shift from the Coulomb one, in its standard errors
+                v["mean_shift_over_sigma"] = float(f"{d.mean() / sbar:.3e}")
             v["var_x_time"] = float(f"{blocking(vals, 100)[1] ** 2 * el:.6g}")
         out_vars[vname] = v
         progress(f"{name} {vname}: {v['steps_per_s']} steps/s")
