@@ -186,12 +186,12 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     c->precision = precision;
     c->want_grad = want_grad;
     c->lambda = lambda;
-    // low-precision operand layout: K extents (reals) padded to multiples of the
-    // K chunk of the low-precision Green's-function kernel (32 FP32, 64 BF16/FP16)
-    const int kq = precision == MCMP2_FP32 ? 32 : 64;
+    // BF16 / FP16 operand layout: K extents (reals) padded to multiples of the
+    // K chunk (64) of their Green's-function kernels
+    const int kq = 64;
     c->Ko = (2 * n_occ + kq - 1) / kq * kq;
     c->Ktot = c->Ko + (2 * n_vir + kq - 1) / kq * kq;
-    const size_t op_bytes = precision == MCMP2_FP32 ? 4 : 2;
+    const size_t op_bytes = 2;
 
     // N_g = sum over all pairs of weight-function Gaussians (Sec. III).
     std::vector<double> gpar(4 * (size_t)c->n_nuc);
@@ -232,7 +232,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(dalloc(&c->hinv, (size_t)c->m_pad));
     TRY(dalloc(&c->rhat, 4 * (size_t)c->m_pad));
     TRY(dalloc(&c->psi, 2 * (size_t)nsp * c->R));  // double2 (FP64) or float2 (low precision)
-    if (precision != MCMP2_FP64) {
+    if (precision == MCMP2_BF16 || precision == MCMP2_FP16) {
         unsigned char *u = nullptr;
         const size_t ub = op_bytes * (size_t)n_tau_max * c->R * c->Ktot;
         TRY(dalloc(&u, ub));
@@ -262,7 +262,9 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(dalloc(&c->wtau, (size_t)n_tau_max));
     std::vector<int> work;
     // bytes of one block tile's operand rows: 8 kTileWalkers rows of all spinors
-    const double row_bytes = precision == MCMP2_FP64 ? 16.0 * nsp : (double)op_bytes * c->Ktot;
+    const double row_bytes = precision == MCMP2_FP64 ? 16.0 * nsp
+                             : precision == MCMP2_FP32 ? 8.0 * nsp
+                                                       : (double)op_bytes * c->Ktot;
     build_green_work(c->T, 8.0 * kTileWalkers * row_bytes, work);
     c->n_slots = 4 * (int)work.size();
     TRY(dalloc(&c->tiles, 2 * (size_t)c->n_tp));
@@ -352,7 +354,8 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
     if ((rc = timed(c, MCMP2_K_SPINOR_GEMM, "spinor_gemm", [&] { return launch_spinor_gemm(c); })) != MCMP2_OK)
         return rc;
     if ((rc = timed(c, MCMP2_K_GREEN_CONTRACT, "green_contract", [&] {
-             return c->precision == MCMP2_FP64 ? launch_green_contract(c, n_tau, grad) : launch_green_lp(c, n_tau, grad);
+             return c->precision == MCMP2_FP64 || c->precision == MCMP2_FP32 ? launch_green_contract(c, n_tau, grad)
+                                                                             : launch_green_lp(c, n_tau, grad);
          })) != MCMP2_OK)
         return rc;
     if ((rc = timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); })) != MCMP2_OK)

@@ -1,5 +1,6 @@
 // Green's functions and pair contraction of the MC-MP2 integrand (Sec. III
-// of the paper, the G+ / G- definitions and Eq. redundant), FP64.
+// of the paper, the G+ / G- definitions and Eq. redundant), FP64 and FP32
+// operands (FP64 contraction in both).
 //
 // For tau sample t the operands are the spinor values psi[k][r] scaled by
 //   s_k = exp(+eps_k tau)  (occupied, G-)   or   exp(-eps_k tau)  (virtual, G+),
@@ -117,37 +118,74 @@ __device__ inline void reduce_tau(const double *__restrict__ partial, int n_slot
 // 32 rows of the Q range, both [k][row] with the row fastest.
 constexpr int KC = 16;
 
-// One K-step of 4 spinors: the three real products T1, T2, T3 of the 3M form
-// (x = P-range operand, scaled per tau; y = Q-range operand).
-template <int NT>
-__device__ inline void mfma_kstep(const double2 *__restrict__ pa, const double2 *__restrict__ pb,
-                                  const double (&s)[NT], d4v (&t1)[NT], d4v (&t2)[NT], d4v (&t3)[NT]) {
-    const double2 x = *pa, y = *pb;
-    const double xs = x.x + x.y, yd = y.x - y.y;
-    double a[NT], b[NT], ab[NT];
+// Operand type of the Green's GEMM: FP64 (FP64 mode) or FP32 (FP32 mode; psi
+// from the FP32 spinor GEMM, FP32 MFMA accumulation, the contraction in FP64
+// as in FP64 mode).  FP64 uses the 3M form (T1, T2, T3); FP32 keeps the four
+// real products (re and im accumulators in T1, T2): its error budget against
+// the FP64 result is set by FP32 rounding and 3M would loosen it.
+template <typename T>
+struct GOp;
+template <>
+struct GOp<double> {
+    using V2 = double2;
+    using Acc = d4v;
+    static constexpr bool M3 = true;
+    __device__ static Acc mfma(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int v, int lk) { return 4 * v + lk; }  // MFMA f64 result row of element v
+};
+template <>
+struct GOp<float> {
+    using V2 = float2;
+    typedef float Acc __attribute__((ext_vector_type(4)));
+    static constexpr bool M3 = false;
+    __device__ static Acc mfma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int v, int lk) { return 4 * lk + v; }  // MFMA f32 result row of element v
+};
+
+// One K-step of 4 spinors (x = P-range operand, scaled per tau; y = Q-range
+// operand).  FP64: the three real products of the 3M form into t1, t2, t3;
+// FP32: Re G into t1 (a c + b d), Im G into t2 (b c - a d).
+template <typename T, int NT>
+__device__ inline void mfma_kstep(const typename GOp<T>::V2 *__restrict__ pa, const typename GOp<T>::V2 *__restrict__ pb,
+                                  const double (&s)[NT], typename GOp<T>::Acc (&t1)[NT],
+                                  typename GOp<T>::Acc (&t2)[NT], typename GOp<T>::Acc (&t3)[NT]) {
+    using O = GOp<T>;
+    const typename O::V2 x = *pa, y = *pb;
+    T a[NT], b[NT];
     for (int t = 0; t < NT; ++t) {
-        a[t] = x.x * s[t];
-        b[t] = x.y * s[t];
-        ab[t] = xs * s[t];
+        a[t] = x.x * (T)s[t];
+        b[t] = x.y * (T)s[t];
     }
-    for (int t = 0; t < NT; ++t) t1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], y.x, t1[t], 0, 0, 0);
-    for (int t = 0; t < NT; ++t) t2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t], y.y, t2[t], 0, 0, 0);
-    for (int t = 0; t < NT; ++t) t3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab[t], yd, t3[t], 0, 0, 0);
+    if constexpr (O::M3) {
+        const T xs = x.x + x.y, yd = y.x - y.y;
+        T ab[NT];
+        for (int t = 0; t < NT; ++t) ab[t] = xs * (T)s[t];
+        for (int t = 0; t < NT; ++t) t1[t] = O::mfma(a[t], y.x, t1[t]);
+        for (int t = 0; t < NT; ++t) t2[t] = O::mfma(b[t], y.y, t2[t]);
+        for (int t = 0; t < NT; ++t) t3[t] = O::mfma(ab[t], yd, t3[t]);
+    } else {
+        for (int t = 0; t < NT; ++t) t1[t] = O::mfma(a[t], y.x, t1[t]);
+        for (int t = 0; t < NT; ++t) t2[t] = O::mfma(b[t], y.x, t2[t]);
+        for (int t = 0; t < NT; ++t) t1[t] = O::mfma(b[t], y.y, t1[t]);
+        for (int t = 0; t < NT; ++t) t2[t] = O::mfma(-a[t], y.y, t2[t]);
+    }
 }
 
-__device__ inline void chunk_load(const double2 *__restrict__ psi, int R, int rp, int rq, int kc, int k_hi, int e0,
-                                  int e1, double2 &ra0, double2 &ra1, double2 &rb0, double2 &rb1) {
+template <typename V2>
+__device__ inline void chunk_load(const V2 *__restrict__ psi, int R, int rp, int rq, int kc, int k_hi, int e0, int e1,
+                                  V2 &ra0, V2 &ra1, V2 &rb0, V2 &rb1) {
     const int k0 = kc + (e0 >> 5), k1 = kc + (e1 >> 5);
     const size_t o0 = (size_t)k0 * R + (e0 & 31), o1 = (size_t)k1 * R + (e1 & 31);
-    const double2 z = {0.0, 0.0};
+    const V2 z = {0, 0};
     ra0 = k0 < k_hi ? psi[o0 + rp] : z;
     rb0 = k0 < k_hi ? psi[o0 + rq] : z;
     ra1 = k1 < k_hi ? psi[o1 + rp] : z;
     rb1 = k1 < k_hi ? psi[o1 + rq] : z;
 }
 
-__device__ inline void chunk_store(double2 (*buf)[KC][32], int e0, int e1, const double2 &ra0, const double2 &ra1,
-                                   const double2 &rb0, const double2 &rb1) {
+template <typename V2>
+__device__ inline void chunk_store(V2 (*buf)[KC][32], int e0, int e1, const V2 &ra0, const V2 &ra1, const V2 &rb0,
+                                   const V2 &rb1) {
     buf[0][e0 >> 5][e0 & 31] = ra0;
     buf[1][e0 >> 5][e0 & 31] = rb0;
     buf[0][e1 >> 5][e1 & 31] = ra1;
@@ -163,10 +201,12 @@ __device__ inline double scale_load(const double *__restrict__ sc, int nsp, int 
 // Stream spinors k in [k_lo, k_hi) through the LDS panels in chunks of KC
 // (the next chunk's global loads are in flight while the current one feeds
 // the MFMAs) and accumulate this wave's sub-tile for NT tau samples.
-template <int NT>
-__device__ inline void stream_k(const double2 *__restrict__ psi, const double *__restrict__ sc, int nsp, int R,
-                                int rp, int rq, int k_lo, int k_hi, double2 (*panel)[2][KC][32],
-                                double (*spanel)[4 * KC], d4v (&t1)[NT], d4v (&t2)[NT], d4v (&t3)[NT]) {
+template <typename T, int NT>
+__device__ inline void stream_k(const typename GOp<T>::V2 *__restrict__ psi, const double *__restrict__ sc, int nsp,
+                                int R, int rp, int rq, int k_lo, int k_hi, typename GOp<T>::V2 (*panel)[2][KC][32],
+                                double (*spanel)[4 * KC], typename GOp<T>::Acc (&t1)[NT],
+                                typename GOp<T>::Acc (&t2)[NT], typename GOp<T>::Acc (&t3)[NT]) {
+    using V2 = typename GOp<T>::V2;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wp = wave >> 1, wq = wave & 1;
@@ -176,7 +216,7 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
     // (Plain scalars here: a lambda version over register arrays crashes the
     // ROCm 7.2 AMDGPU backend in machine copy propagation.)
     const int e0 = tid, e1 = tid + 256;
-    double2 ra0, ra1, rb0, rb1;
+    V2 ra0, ra1, rb0, rb1;
     double sv;
     const int n_chunks = (k_hi - k_lo + KC - 1) / KC;
     chunk_load(psi, R, rp, rq, k_lo, k_hi, e0, e1, ra0, ra1, rb0, rb1);
@@ -197,8 +237,8 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
         for (int ks = 0; ks < KC; ks += 4) {
             double s[NT];
             for (int t = 0; t < NT; ++t) s[t] = spanel[buf][t * KC + ks + lk];
-            mfma_kstep<NT>(&panel[buf][0][ks + lk][16 * wp + li], &panel[buf][1][ks + lk][16 * wq + li], s, t1, t2,
-                           t3);
+            mfma_kstep<T, NT>(&panel[buf][0][ks + lk][16 * wp + li], &panel[buf][1][ks + lk][16 * wq + li], s, t1,
+                              t2, t3);
         }
         if (c + 1 < n_chunks) {
             chunk_store(panel[buf ^ 1], e0, e1, ra0, ra1, rb0, rb1);
@@ -208,28 +248,44 @@ __device__ inline void stream_k(const double2 *__restrict__ psi, const double *_
     }
 }
 
+// G entry v of a lane's accumulators from the GEMM's partial sums
+template <typename T>
+__device__ inline cplx g_entry(const typename GOp<T>::Acc &t1, const typename GOp<T>::Acc &t2,
+                               const typename GOp<T>::Acc &t3, int v) {
+    if constexpr (GOp<T>::M3)
+        return {t1[v] + t2[v], (t3[v] - t1[v]) + t2[v]};
+    else
+        return {(double)t1[v], (double)t2[v]};
+}
+
 // grid: (n_slots / 4, tau chunks); block (x, y) takes work item x and tau
-// samples t0 .. t0 + NT - 1, t0 = y NT.
+// samples t0 .. t0 + NT - 1, t0 = y NT.  T: operand type (double / float).
 // GRAD: also write, per walker pair, the 8x8 blocks of the Hermitian adjoint
 // matrices H- and H+ (gradient of the step value with respect to the entries
 // of G- and G+, folded as Gbar + Gbar^H) into Hm / Hp [n_tau][R][R] complex.
 // BREIT: Gaunt / Breit interaction in the contraction (no gradients; rhat
 // [m_pad][4] unit vectors of r1p - r2p, gauge = weight of the second Breit term).
-template <int NT, bool GRAD, bool BREIT>
+template <typename T, int NT, bool GRAD, bool BREIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD && !BREIT ? 4 : 2))) void
-green_contract_kernel(const double *__restrict__ psi_, const double *__restrict__ scale,
+green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ scale,
                       const double *__restrict__ wtau, const double *__restrict__ hinv, const int *__restrict__ tiles,
                       const int *__restrict__ work, int n_slots, int R, int no, int nsp, int m,
                       double *__restrict__ partial, double2 *__restrict__ Hm, double2 *__restrict__ Hp, double cgrad,
                       const double *__restrict__ rhat, double gauge) {
+    using O = GOp<T>;
+    using V2 = typename O::V2;
+    using Acc = typename O::Acc;
     const int t0 = (int)blockIdx.y * NT;
-    // 2 buffers x (A, B) x KC x 32 complex = 32 KB; reused for the G tiles of the epilogue
-    __shared__ double2 panel[2][2][KC][32];
+    // 2 buffers x (A, B) x KC x 32 complex operands (32 KB FP64, 16 KB FP32),
+    // reused for the FP64 G tiles of the epilogue (4 waves x 512 complex = 32 KB)
+    constexpr int PANEL_BYTES = 2 * 2 * KC * 32 * (int)sizeof(V2);
+    constexpr int EPI_BYTES = 4 * 512 * (int)sizeof(cplx);
+    __shared__ __align__(16) unsigned char smem[PANEL_BYTES > EPI_BYTES ? PANEL_BYTES : EPI_BYTES];
     __shared__ double spanel[2][4 * KC];  // tau scalings of the buffered chunks
-    const double2 *psi = reinterpret_cast<const double2 *>(psi_);
+    V2(*panel)[2][KC][32] = reinterpret_cast<V2(*)[2][KC][32]>(smem);
+    const V2 *psi = reinterpret_cast<const V2 *>(psi_);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wp = wave >> 1, wq = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
     const int item = work[blockIdx.x];
     if (item < 0) {  // padding block: zero partials
@@ -244,32 +300,33 @@ green_contract_kernel(const double *__restrict__ psi_, const double *__restrict_
     const int rp = 32 * PT, rq = 32 * QT;
     const double *sc = scale + (size_t)t0 * nsp;
 
-    // occupied spinors -> G-, then virtual spinors -> G+ (T1, T2, T3 of the
-    // 3M form; G- is assembled before the G+ pass to free its registers)
-    d4v gm_re[NT], gm_im[NT];
+    // occupied spinors -> G-, then virtual spinors -> G+; G- is assembled
+    // (FP64) before the G+ pass to free its partial sums' registers
+    cplx gm[NT][4];
     {
-        d4v m1[NT], m2[NT], m3[NT];
-        for (int t = 0; t < NT; ++t) m1[t] = m2[t] = m3[t] = d4v{0.0, 0.0, 0.0, 0.0};
-        stream_k<NT>(psi, sc, nsp, R, rp, rq, 0, no, panel, spanel, m1, m2, m3);
-        for (int t = 0; t < NT; ++t) {
-            gm_re[t] = m1[t] + m2[t];
-            gm_im[t] = (m3[t] - m1[t]) + m2[t];
-        }
+        Acc m1[NT], m2[NT], m3[NT];
+        for (int t = 0; t < NT; ++t) m1[t] = m2[t] = m3[t] = Acc{0, 0, 0, 0};
+        stream_k<T, NT>(psi, sc, nsp, R, rp, rq, 0, no, panel, spanel, m1, m2, m3);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gm[t][v] = g_entry<T>(m1[t], m2[t], m3[t], v);
     }
-    d4v p1[NT], p2[NT], p3[NT];
-    for (int t = 0; t < NT; ++t) p1[t] = p2[t] = p3[t] = d4v{0.0, 0.0, 0.0, 0.0};
-    stream_k<NT>(psi, sc, nsp, R, rp, rq, no, nsp, panel, spanel, p1, p2, p3);
+    Acc p1[NT], p2[NT], p3[NT];
+    for (int t = 0; t < NT; ++t) p1[t] = p2[t] = p3[t] = Acc{0, 0, 0, 0};
+    stream_k<T, NT>(psi, sc, nsp, R, rp, rq, no, nsp, panel, spanel, p1, p2, p3);
 
     // epilogue: per tau, stage the wave's G- and G+ sub-tiles in LDS and contract
-    cplx *Gm = reinterpret_cast<cplx *>(&panel[0][0][0][0]) + wave * 512;
+    cplx *Gm = reinterpret_cast<cplx *>(smem) + wave * 512;
     cplx *Gp = Gm + 256;
     const int slot = 4 * blockIdx.x + wave;
 #pragma unroll  // constant indices keep the accumulators in registers
     for (int t = 0; t < NT; ++t) {
+#pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = 4 * v + lk;  // MFMA f64 result row of element v
-            Gm[i * 16 + li] = {gm_re[t][v], gm_im[t][v]};
-            Gp[i * 16 + li] = {p1[t][v] + p2[t][v], (p3[t][v] - p1[t][v]) + p2[t][v]};
+            const int i = O::row(v, lk);
+            Gm[i * 16 + li] = gm[t][v];
+            Gp[i * 16 + li] = g_entry<T>(p1[t], p2[t], p3[t], v);
         }
         __syncthreads();
         if constexpr (BREIT)
@@ -298,32 +355,45 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ 
 // ~2.5 MB of an XCD's 4 MB L2.  Super-blocks go to the 8 XCD lists largest
 // first to the least loaded list; the lists are padded to equal length (-1)
 // and interleaved so that workgroup b (dispatched to XCD b mod 8) takes entry
-// b / 8 of list b mod 8.
+// b / 8 of list b mod 8.  Every XCD then works through its own list, so the
+// launch lasts as long as the longest one: B is the widest band within the L2
+// budget whose lists come within 3% of each other (at 128 walker pairs the L2
+// budget alone would allow 7-tile bands, 15 super-blocks and a longest list
+// 17% above the mean; 6 with FP32 operands, leaving two XCDs idle).
 void build_green_work(int T, double tile_bytes, std::vector<int> &work) {
     constexpr int kXcd = 8;
-    int B = (int)std::max(1.0, 2.5e6 / (2.0 * tile_bytes));
-    B = std::min(B, T);
-    const int nbands = (T + B - 1) / B;
     auto tp_index = [T](int P, int Q) { return P * T - P * (P - 1) / 2 + (Q - P); };
-    std::vector<std::vector<int>> blocks;
-    for (int I = 0; I < nbands; ++I)
-        for (int J = I; J < nbands; ++J) {
-            std::vector<int> items;
-            for (int P = I * B; P < std::min(T, (I + 1) * B); ++P)
-                for (int Q = std::max(P, J * B); Q < std::min(T, (J + 1) * B); ++Q) items.push_back(tp_index(P, Q));
-            if (!items.empty()) blocks.push_back(std::move(items));
+    auto deal = [&](int B, std::vector<std::vector<int>> &lists) {
+        const int nbands = (T + B - 1) / B;
+        std::vector<std::vector<int>> blocks;
+        for (int I = 0; I < nbands; ++I)
+            for (int J = I; J < nbands; ++J) {
+                std::vector<int> items;
+                for (int P = I * B; P < std::min(T, (I + 1) * B); ++P)
+                    for (int Q = std::max(P, J * B); Q < std::min(T, (J + 1) * B); ++Q)
+                        items.push_back(tp_index(P, Q));
+                if (!items.empty()) blocks.push_back(std::move(items));
+            }
+        std::stable_sort(blocks.begin(), blocks.end(),
+                         [](const std::vector<int> &x, const std::vector<int> &y) { return x.size() > y.size(); });
+        lists.assign(kXcd, {});
+        for (auto &blk : blocks) {
+            size_t best = 0;
+            for (size_t x = 1; x < lists.size(); ++x)
+                if (lists[x].size() < lists[best].size()) best = x;
+            lists[best].insert(lists[best].end(), blk.begin(), blk.end());
         }
-    std::stable_sort(blocks.begin(), blocks.end(),
-                     [](const std::vector<int> &x, const std::vector<int> &y) { return x.size() > y.size(); });
-    std::vector<std::vector<int>> lists(kXcd);
-    for (auto &blk : blocks) {
-        size_t best = 0;
-        for (size_t x = 1; x < lists.size(); ++x)
-            if (lists[x].size() < lists[best].size()) best = x;
-        lists[best].insert(lists[best].end(), blk.begin(), blk.end());
-    }
-    size_t len = 0;
-    for (auto &l : lists) len = std::max(len, l.size());
+        size_t len = 0;
+        for (auto &l : lists) len = std::max(len, l.size());
+        return len;
+    };
+    const int b_l2 = std::min(T, std::max(1, (int)(2.5e6 / (2.0 * tile_bytes))));
+    const double mean = (double)T * (T + 1) / 2 / kXcd;
+    std::vector<std::vector<int>> lists;
+    int B = b_l2;
+    for (; B > 1; --B)
+        if (deal(B, lists) <= 1.03 * mean) break;
+    const size_t len = deal(B, lists);
     work.assign(kXcd * len, -1);
     for (size_t b = 0; b < work.size(); ++b) {
         const auto &l = lists[b % kXcd];
@@ -349,36 +419,57 @@ int green_tau_chunk(int nblocks, int n_tau, int n_cu) {
     return 1;
 }
 
+namespace {
+
+// One launch of NTV tau samples per block: the gradient variant, the Gaunt /
+// Breit variant (FP64, one tau per block only) or the plain estimator.
+template <typename T, int NTV>
+void launch_green_nt(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, double cgrad) {
+    double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
+    if (grad) {
+        green_contract_kernel<T, NTV, true, false><<<grid, 256, 0, c->stream>>>(
+            c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,
+            c->partial, Hm, Hp, cgrad, c->rhat, 0.0);
+        return;
+    }
+    if constexpr (NTV == 1 && __is_same(T, double)) {
+        if (breit) {
+            const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
+            green_contract_kernel<double, 1, false, true><<<grid, 256, 0, c->stream>>>(
+                c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,
+                c->partial, nullptr, nullptr, 0.0, c->rhat, gauge);
+            return;
+        }
+    }
+    green_contract_kernel<T, NTV, false, false><<<grid, 256, 0, c->stream>>>(
+        c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m, c->partial,
+        nullptr, nullptr, 0.0, c->rhat, 0.0);
+}
+
+template <typename T>
+void launch_green_typed(const mcmp2_ctx *c, dim3 grid, int nt, bool grad, bool breit, double cgrad) {
+    if (nt == 1)
+        launch_green_nt<T, 1>(c, grid, grad, breit, cgrad);
+    else
+        launch_green_nt<T, 2>(c, grid, grad, breit, cgrad);
+}
+
+}  // namespace
+
+// FP64 and FP32 modes (the operand type follows the context's precision).
 hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
     // gradient of the step value (mean over tau of the pair average): c = -1/2 / (mC2 n_tau)
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
-    double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
     const int nblocks = c->n_slots / 4;  // one work-list entry per block, four partial slots
-    const bool breit = c->interaction != MCMP2_COULOMB;  // mcmp2_step rejects gradients with it
+    const bool breit = c->interaction != MCMP2_COULOMB;  // FP64 only; mcmp2_step rejects gradients with it
     // one tau per block with the Gaunt / Breit contraction: its epilogue
     // needs the registers that a second tau's accumulators would hold
     const int nt = breit ? 1 : green_tau_chunk(nblocks, n_tau, c->n_cu);
     const dim3 grid(nblocks, n_tau / nt);
-    const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
-#define LAUNCH(NTV)                                                                                              \
-    if (grad)                                                                                                    \
-        green_contract_kernel<NTV, true, false><<<grid, 256, 0, c->stream>>>(                                    \
-            c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,        \
-            c->partial, Hm, Hp, cgrad, c->rhat, 0.0);                                                            \
-    else if (breit)                                                                                              \
-        green_contract_kernel<NTV, false, true><<<grid, 256, 0, c->stream>>>(                                    \
-            c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,        \
-            c->partial, nullptr, nullptr, 0.0, c->rhat, gauge);                                                  \
-    else                                                                                                         \
-        green_contract_kernel<NTV, false, false><<<grid, 256, 0, c->stream>>>(                                   \
-            c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,        \
-            c->partial, nullptr, nullptr, 0.0, c->rhat, 0.0)
-    if (nt == 1) {
-        LAUNCH(1);
-    } else {
-        LAUNCH(2);
-    }
-#undef LAUNCH
+    if (c->precision == MCMP2_FP32)
+        launch_green_typed<float>(c, grid, nt, grad, breit, cgrad);
+    else
+        launch_green_typed<double>(c, grid, nt, grad, breit, cgrad);
     return hipGetLastError();
 }
 

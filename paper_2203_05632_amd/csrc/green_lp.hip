@@ -1,6 +1,7 @@
-// Low-precision Green's functions (FP32, BF16, FP16 operands on MFMA with
-// FP32 accumulation) followed by the same FP64 pair contraction as the FP64
-// path (Sec. III of the paper: G+ / G- and the redundant-walker estimator).
+// Low-precision Green's functions (BF16, FP16 operands on MFMA with FP32
+// accumulation) followed by the pair contraction in FP32 arithmetic with FP64
+// weights and sums (Sec. III of the paper: G+ / G- and the redundant-walker
+// estimator).  FP32 mode runs the FP64 kernel's structure (green.hip).
 //
 // Operands.  For tau sample t, lp_operands writes
 //   U_t[row][K] = psi[k][row] * sqrt(s_t[k]),  K = 2 k (+1 for the imaginary part),
@@ -28,13 +29,12 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-// Reals of K per LDS chunk (FP32: 32 = one pass of 8 K-steps over 4 lane
-// groups; BF16/FP16: 64 = two 16x16x32 K-steps) and the padded LDS row
-// length: 16 extra bytes per row so that the 16-byte reads of 8 consecutive
-// rows fall in distinct banks.
+// Reals of K per LDS chunk (64 = two 16x16x32 K-steps) and the padded LDS
+// row length: 16 extra bytes per row so that the 16-byte reads of 8
+// consecutive rows fall in distinct banks.
 template <typename T>
 constexpr int lkc() {
-    return sizeof(T) == 4 ? 32 : 64;
+    return 64;
 }
 template <typename T>
 constexpr int lrow() {
@@ -43,10 +43,6 @@ constexpr int lrow() {
 
 template <typename T>
 __device__ inline T to_op(double v);
-template <>
-__device__ inline float to_op<float>(double v) {
-    return (float)v;
-}
 template <>
 __device__ inline __bf16 to_op<__bf16>(double v) {
     return (__bf16)v;
@@ -90,10 +86,6 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
 template <typename T>
 struct Mfma;
 template <>
-struct Mfma<float> {  // v_mfma_f32_16x16x4f32: lane holds A[l%16][l/16], B[l/16][l%16]
-    static constexpr int K = 4;
-};
-template <>
 struct Mfma<__bf16> {  // v_mfma_f32_16x16x32_bf16: lane holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16]
     static constexpr int K = 32;
 };
@@ -104,27 +96,14 @@ struct Mfma<_Float16> {
 
 // One chunk of this wave's 16x16 sub-tile for NT tau samples.  pa / pb:
 // [NT][32 rows][lrow] operand panels (A rows of the P range, B rows of the Q
-// range).  Every lane reads 8 consecutive K values of its row per MFMA group:
-// FP32 lane group lk owns K = 8 lk + j of the chunk and feeds them to 8
-// successive 16x16x4 MFMAs (a dot product does not depend on how K is split
-// over the steps), so the re/im partner of every value sits in the same lane.
+// range).  Every lane reads 8 consecutive K values of its row per MFMA, so
+// the re/im partner of every value sits in the same lane.
 template <typename T, int NT>
 __device__ __attribute__((always_inline)) inline void lp_chunk(const T *pa, const T *pb, int wp, int wq, f4v (&re)[NT], f4v (&im)[NT]) {
     constexpr int LR = lrow<T>();
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     typedef T v8 __attribute__((ext_vector_type(8)));
-    if constexpr (Mfma<T>::K == 4) {
-        for (int t = 0; t < NT; ++t) {
-            const v8 a = *reinterpret_cast<const v8 *>(pa + (t * 32 + 16 * wp + li) * LR + 8 * lk);
-            const v8 b = *reinterpret_cast<const v8 *>(pb + (t * 32 + 16 * wq + li) * LR + 8 * lk);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float w = (j & 1) ? b[j - 1] : -b[j + 1];  // W = (-im, re)
-                re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], re[t], 0, 0, 0);
-                im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], w, im[t], 0, 0, 0);
-            }
-        }
-    } else {
+    {
 #pragma unroll
         for (int ks = 0; ks < lkc<T>(); ks += 32)
             for (int t = 0; t < NT; ++t) {
@@ -240,12 +219,11 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
             Gp[i * 16 + li] = {(double)gp_re[t][v], (double)gp_im[t][v]};
         }
         __syncthreads();
-        // FP32 contraction arithmetic with BF16 / FP16 operands, FP64 with FP32 operands
-        contract_pairs<GRAD, HT, std::conditional_t<sizeof(T) == 2, float, double>>(Gm, Gp, PT, QT, m, hinv,
-                                                                                   wtau[t0 + t], cgrad, R,
-                             partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
-                             GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
-                             GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
+        // FP32 contraction arithmetic (weights and sums in FP64)
+        contract_pairs<GRAD, HT, float>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
+                                        partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
+                                        GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
+                                        GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
         __syncthreads();
     }
 }
@@ -436,45 +414,29 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     if constexpr (sizeof(T) == 2)
         if (green_big_selected(c, n_tau)) return launch_big_typed<T>(c, n_tau, grad);
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
-    using HT = std::conditional_t<sizeof(T) == 4, double2, uint32_t>;
-    HT *Hm = reinterpret_cast<HT *>(c->Hm), *Hp = reinterpret_cast<HT *>(c->Hp);
+    uint32_t *Hm = reinterpret_cast<uint32_t *>(c->Hm), *Hp = reinterpret_cast<uint32_t *>(c->Hp);
     const int nblocks = c->n_slots / 4;
+    constexpr int NTMAX = 4;
+    for (int t0 = 0; t0 < n_tau; t0 += NTMAX) {
+        const int nt = std::min(NTMAX, n_tau - t0);
 #define LP_LAUNCH(NTV)                                                                                           \
     if (grad)                                                                                                    \
-        green_lp_kernel<T, NTV, true, HT><<<grid, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,         \
-                                                                   c->tiles, c->work, c->n_slots, c->R, c->m,   \
-                                                                   t0, c->partial, Hm, Hp, cgrad);              \
+        green_lp_kernel<T, NTV, true, uint32_t><<<nblocks, 256, 0, c->stream>>>(                                 \
+            U, c->Ko, c->Ktot, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->m, t0, c->partial, Hm,  \
+            Hp, cgrad);                                                                                          \
     else                                                                                                         \
-        green_lp_kernel<T, NTV, false, HT><<<grid, 256, 0, c->stream>>>(U, c->Ko, c->Ktot, c->wtau, c->hinv,        \
-                                                                    c->tiles, c->work, c->n_slots, c->R, c->m,  \
-                                                                    t0, c->partial, nullptr, nullptr, 0.0)
-    if constexpr (sizeof(T) == 4) {
-        // FP32: one launch, tau chunks in the grid's second dimension, NT
-        // (at most 2: FP32 panels are twice as large) from the same makespan
-        // model as the FP64 kernel
-        const int nt = green_tau_chunk(nblocks, n_tau, c->n_cu), t0 = 0;
-        const dim3 grid(nblocks, n_tau / nt);
-        if (nt == 1) {
-            LP_LAUNCH(1);
-        } else {
-            LP_LAUNCH(2);
+        green_lp_kernel<T, NTV, false, uint32_t><<<nblocks, 256, 0, c->stream>>>(                                \
+            U, c->Ko, c->Ktot, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->m, t0, c->partial,      \
+            nullptr, nullptr, 0.0)
+        switch (nt) {
+            case 1: LP_LAUNCH(1); break;
+            case 2: LP_LAUNCH(2); break;
+            case 3: LP_LAUNCH(3); break;
+            default: LP_LAUNCH(4); break;
         }
-        return hipGetLastError();
-    } else {
-        constexpr int NTMAX = 4;
-        const dim3 grid(nblocks);
-        for (int t0 = 0; t0 < n_tau; t0 += NTMAX) {
-            const int nt = std::min(NTMAX, n_tau - t0);
-            switch (nt) {
-                case 1: LP_LAUNCH(1); break;
-                case 2: LP_LAUNCH(2); break;
-                case 3: LP_LAUNCH(3); break;
-                default: LP_LAUNCH(4); break;
-            }
 #undef LP_LAUNCH
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -498,7 +460,6 @@ void build_big_tiles(int T16, std::vector<int> &tiles) {
 
 hipError_t launch_green_lp(const mcmp2_ctx *c, int n_tau, bool grad) {
     switch (c->precision) {
-        case MCMP2_FP32: return launch_lp_typed<float>(c, n_tau, grad);
         case MCMP2_BF16: return launch_lp_typed<__bf16>(c, n_tau, grad);
         default: return launch_lp_typed<_Float16>(c, n_tau, grad);
     }
