@@ -355,11 +355,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ 
 // ~2.5 MB of an XCD's 4 MB L2.  Super-blocks go to the 8 XCD lists largest
 // first to the least loaded list; the lists are padded to equal length (-1)
 // and interleaved so that workgroup b (dispatched to XCD b mod 8) takes entry
-// b / 8 of list b mod 8.  Every XCD then works through its own list, so the
-// launch lasts as long as the longest one: B is the widest band within the L2
-// budget whose lists come within 3% of each other (at 128 walker pairs the L2
-// budget alone would allow 7-tile bands, 15 super-blocks and a longest list
-// 17% above the mean; 6 with FP32 operands, leaving two XCDs idle).
+// b / 8 of list b mod 8.  Every XCD then works through its own list: B is the
+// widest band within the L2 budget whose longest list is at most 20% above
+// the mean.  (At 128 walker pairs the L2 budget alone allows 14-tile bands
+// for FP32 rows and 27-tile bands for BF16 rows: 6 and 3 super-blocks, two and
+// five XCDs idle.  A 3% bound, i.e. narrower bands, measured no faster and
+// doubled the FP64 kernel's HBM reads.)
 void build_green_work(int T, double tile_bytes, std::vector<int> &work) {
     constexpr int kXcd = 8;
     auto tp_index = [T](int P, int Q) { return P * T - P * (P - 1) / 2 + (Q - P); };
@@ -392,7 +393,7 @@ void build_green_work(int T, double tile_bytes, std::vector<int> &work) {
     std::vector<std::vector<int>> lists;
     int B = b_l2;
     for (; B > 1; --B)
-        if (deal(B, lists) <= 1.03 * mean) break;
+        if (deal(B, lists) <= 1.2 * mean) break;
     const size_t len = deal(B, lists);
     work.assign(kXcd * len, -1);
     for (size_t b = 0; b < work.size(); ++b) {
