@@ -218,5 +218,9 @@ hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau) {
         reinterpret_cast<const float2 *>(c->psi), c->scale, c->R, c->nsp, n_tau, c->Vt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_adj_typed<64>(c, tau, n_tau);
+    // 128-column tiles once they give every CU a block (the 512-pair workload:
+    // 416 tiles, 1028 us against 1186 us with 64-column tiles); below that the
+    // narrower tiles' extra blocks win (128 pairs: 32 tiles, 101 against 67 us)
+    const int wide_items = ((c->R + ABM - 1) / ABM) * ((c->no + 127) / 128 + (c->nsp - c->no + 127) / 128);
+    return wide_items >= c->n_cu ? launch_adj_typed<64>(c, tau, n_tau) : launch_adj_typed<32>(c, tau, n_tau);
 }
