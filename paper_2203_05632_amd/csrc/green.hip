@@ -423,7 +423,7 @@ int green_tau_chunk(int nblocks, int n_tau, int n_cu) {
 namespace {
 
 // One launch of NTV tau samples per block: the gradient variant, the Gaunt /
-// Breit variant (FP64, one tau per block only) or the plain estimator.
+// Breit variant (one tau per block only) or the plain estimator.
 template <typename T, int NTV>
 void launch_green_nt(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, double cgrad) {
     double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
@@ -433,10 +433,10 @@ void launch_green_nt(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, doubl
             c->partial, Hm, Hp, cgrad, c->rhat, 0.0);
         return;
     }
-    if constexpr (NTV == 1 && __is_same(T, double)) {
+    if constexpr (NTV == 1) {
         if (breit) {
             const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
-            green_contract_kernel<double, 1, false, true><<<grid, 256, 0, c->stream>>>(
+            green_contract_kernel<T, 1, false, true><<<grid, 256, 0, c->stream>>>(
                 c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,
                 c->partial, nullptr, nullptr, 0.0, c->rhat, gauge);
             return;
@@ -462,7 +462,7 @@ hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
     // gradient of the step value (mean over tau of the pair average): c = -1/2 / (mC2 n_tau)
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     const int nblocks = c->n_slots / 4;  // one work-list entry per block, four partial slots
-    const bool breit = c->interaction != MCMP2_COULOMB;  // FP64 only; mcmp2_step rejects gradients with it
+    const bool breit = c->interaction != MCMP2_COULOMB;  // mcmp2_step rejects gradients with it
     // one tau per block with the Gaunt / Breit contraction: its epilogue
     // needs the registers that a second tau's accumulators would hold
     const int nt = breit ? 1 : green_tau_chunk(nblocks, n_tau, c->n_cu);

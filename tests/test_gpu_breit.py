@@ -59,6 +59,24 @@ def test_breit_step_matches_oracle(kind, name, over, taus):
         assert np.max(np.abs(ref[t] - coul[t])) > 1e-6 * scale
 
 
+@pytest.mark.parametrize("kind", ["gaunt", "breit"])
+def test_breit_fp32_near_oracle(kind):
+    """FP32 mode runs the same alpha-weighted FP64 contraction on FP32 Green's
+    functions: within the FP32 mode's step bound (1e-6 of the pair scale)."""
+    inp = make_inputs("C1")
+    wk = initial_walkers(inp)
+    taus = [0.3, 1.2]
+    ctx = _ctx(inp, precision="fp32")
+    ctx.set_interaction(kind)
+    got = _gpu_step(ctx, wk, np.array(taus))
+    res, pairs = oi.step_estimate(inp, wk, taus, tau_lambda(inp.eps, inp.n_occ), n_g(inp.nuc_xyz, inp.wfn),
+                                  return_pairs=True, interaction=kind)
+    for t in range(len(taus)):
+        err = rel_err(got[t], res.numpy()[t], norm=float(pairs[t].real.abs().mean()))
+        print(f"fp32 {kind} tau={taus[t]}: error / scale = {err:.3e}", flush=True)
+        assert err < 1e-6
+
+
 def test_switching_back_to_coulomb_is_bitwise_the_default():
     inp = make_inputs("C1")
     wk = initial_walkers(inp)
@@ -83,11 +101,12 @@ def test_breit_step_is_bitwise_deterministic():
     assert np.array_equal(a, b)
 
 
-def test_breit_rejected_outside_fp64_and_with_gradients():
+def test_breit_rejected_in_bf16_fp16_and_with_gradients():
     from paper_2203_05632_amd._lib import MCMP2Error
     inp = make_inputs("C0")
-    with pytest.raises(MCMP2Error, match="FP64"):
-        _ctx(inp, precision="bf16").set_interaction("breit")
+    for prec in ("bf16", "fp16"):
+        with pytest.raises(MCMP2Error, match="FP64"):
+            _ctx(inp, precision=prec).set_interaction("breit")
     ctx = _ctx(inp, want_grad=True)
     ctx.set_interaction("gaunt")
     wk = dev(initial_walkers(inp))
