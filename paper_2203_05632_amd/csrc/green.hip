@@ -328,7 +328,10 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
             Gm[i * 16 + li] = gm[t][v];
             Gp[i * 16 + li] = g_entry<T>(p1[t], p2[t], p3[t], v);
         }
-        __syncthreads();
+        // The staged sub-tiles are private to the wave (the K loop ended with a
+        // block barrier) and one wave's LDS accesses complete in order, so a
+        // wave barrier orders the staging against the contraction's reads.
+        __builtin_amdgcn_wave_barrier();
         if constexpr (BREIT)
             contract_pairs_breit(Gm, Gp, PT, QT, m, hinv, rhat, gauge, wtau[t0 + t],
                                  partial + ((size_t)(t0 + t) * n_slots + slot) * 2);
@@ -337,7 +340,7 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
                                           partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
                                           GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
                                           GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
-        __syncthreads();  // the sub-tiles are rewritten for the next tau
+        __builtin_amdgcn_wave_barrier();  // the sub-tiles are rewritten for the next tau
     }
 }
 

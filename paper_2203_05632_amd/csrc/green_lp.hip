@@ -218,13 +218,15 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
             Gm[i * 16 + li] = {(double)gm_re[t][v], (double)gm_im[t][v]};
             Gp[i * 16 + li] = {(double)gp_re[t][v], (double)gp_im[t][v]};
         }
-        __syncthreads();
+        // wave-private staging (the K loop ended with a block barrier); one
+        // wave's LDS accesses complete in order
+        __builtin_amdgcn_wave_barrier();
         // FP32 contraction arithmetic (weights and sums in FP64)
         contract_pairs<GRAD, HT, float>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
                                         partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
                                         GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
                                         GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -342,7 +344,8 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
     stream(0, Kow, gm_re, gm_im);
     stream(Kow, Ktw, gp_re, gp_im);
 
-    // epilogue: wave-private G rows in LDS, 8 rows (one walker) x 32 columns
+    // epilogue: wave-private G rows in LDS (so wave barriers order the staging
+    // and the reads; the K loop ended with a block barrier), 8 rows (one walker) x 32 columns
     // (four walkers) at a time.  Rows are padded to 36 complex (288 B, i.e.
     // 32 B apart modulo the 256-byte bank row), so the 4-row reads of the
     // contraction hit each bank at most twice.
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
                         Gm[e] = float2{gm_re[i][j][v], gm_im[i][j][v]};
                         Gp[e] = float2{gp_re[i][j][v], gp_im[i][j][v]};
                     }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
             const int p = BW * P + 8 * wr + 2 * i + h, q = BW * Q + 4 * wc + lk;
             double dir, exc;
             contract_pair<GRAD, uint32_t, float>(Gm + 8 * lk, Gp + 8 * lk, GLD, p, q, p < q && q < m, hinv, wt, cgrad,
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
                          x3 = __shfl(exc, 48, 64);
             dsum += ((d0 + d1) + d2) + d3;
             xsum += ((x0 + x1) + x2) + x3;
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
         }
     if (lane == 0) {
         double *out = partial + ((size_t)item * 8 + wave) * 2;
