@@ -84,6 +84,21 @@ struct mcmp2_ctx {
 };
 
 // g(r) of Eq. basisSet; gpar[I] = (c1 N(z1), z1, c2 N(z2), z2).
+// Work items of the spinor GEMMs: (primitive set, spinor tile, point tile).
+// Block b runs on XCD b % 8; each XCD takes a contiguous range of the n_pairs
+// (spinor tile, point tile) pairs and first runs their small-component
+// items (the longer K loop), then the large-component ones, which fill in
+// behind them (longest first; 16 ceil(n_pairs / 8) blocks).  Returns false
+// for a padding block.
+__device__ inline bool spinor_set_item(int n_pairs, int &set, int &pair) {
+    const int pp = (n_pairs + 7) / 8, x = (int)(blockIdx.x % 8), j = (int)(blockIdx.x / 8);
+    const int cnt = min(pp, n_pairs - x * pp);
+    if (j >= 2 * cnt) return false;
+    set = j < cnt ? 1 : 0;
+    pair = x * pp + (j < cnt ? j : j - cnt);
+    return true;
+}
+
 __device__ inline double g_value(double x, double y, double z, const double *nuc, const double *gpar, int n_nuc) {
     double out = 0.0;
     for (int I = 0; I < n_nuc; ++I) {

@@ -207,8 +207,9 @@ __global__ __launch_bounds__(256) void spinor_gemm_kernel(const double *__restri
 // padded by 128 B so that 16 lanes read 128 contiguous bytes and the four
 // K-groups of a wave fall 128 B apart modulo the 256-byte bank row.
 // Work items (spinor tile, point tile, set) are dealt to the XCDs in
-// contiguous ranges (block b runs on XCD b % 8), so the point tiles sharing a
-// coefficient tile read it through one L2.
+// contiguous ranges of tile pairs (spinor_set_item: block b runs on XCD
+// b % 8), so the point tiles sharing a coefficient tile read it through one
+// L2; within a range the longer small-component items go first.
 typedef double d2v __attribute__((ext_vector_type(2)));
 
 template <typename T, int KS, int PTS>
@@ -229,12 +230,8 @@ __global__ __launch_bounds__(256) void spinor_tile_kernel(const double *__restri
     __shared__ __align__(16) double As[2][KC * AROW];
     __shared__ __align__(16) double Bs[2][KC * BROW];
 
-    const int n_items = 2 * n_kt * n_pt;
-    const int per = (n_items + 7) / 8;
-    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (item >= n_items) return;
-    // set fastest: every XCD's range mixes the short (L) and long (S) K loops
-    const int set = item & 1, rest = item >> 1;
+    int set, rest;
+    if (!spinor_set_item(n_kt * n_pt, set, rest)) return;
     const int k0 = (rest / n_pt) * KS, pt0 = (rest % n_pt) * PTS;
     const int mu_lo = set ? nL : 0, mu_hi = set ? nb : nL;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -337,8 +334,7 @@ __global__ __launch_bounds__(256) void spinor_tile_kernel(const double *__restri
 template <typename T, int KS, int PTS>
 hipError_t launch_spinor_tile(const mcmp2_ctx *c) {
     const int n_kt = (c->nsp + KS - 1) / KS, n_pt = (c->E + PTS - 1) / PTS;
-    const int n_items = 2 * n_kt * n_pt;
-    spinor_tile_kernel<T, KS, PTS><<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
+    spinor_tile_kernel<T, KS, PTS><<<16 * ((n_kt * n_pt + 7) / 8), 256, 0, c->stream>>>(
         c->XT, c->coef, c->E, c->nb, c->nL, c->nsp, c->R, n_kt, n_pt, c->psi);
     return hipGetLastError();
 }

@@ -202,11 +202,9 @@ __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict
                                                         int nsp, int nLp, int nSp, int E, int R, int n_rt, int n_ct,
                                                         float2 *__restrict__ psi) {
     __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LKW];
-    const int n_items = 2 * n_rt * n_ct;
-    const int item = xcd_item(n_items);
-    if (item >= n_items) return;
-    // set fastest: every XCD's range mixes the short (L) and long (S) K loops
-    const int set = item & 1, rest = item >> 1, rt = rest / n_ct, ct = rest % n_ct;
+    int set, rest;
+    if (!spinor_set_item(n_rt * n_ct, set, rest)) return;
+    const int rt = rest / n_ct, ct = rest % n_ct;
     const int koff = set ? 3 * nLp : 0, K = 3 * (set ? nSp : nLp), ld = 3 * (nLp + nSp);
     f4v acc[4][4];
     lp_gemm_tile<__bf16>(Cb + koff, ld, LBM * rt, 4 * nsp, Xb + koff, ld, LBM * ct, E, K, lds, acc);
@@ -288,8 +286,7 @@ hipError_t launch_spinor_lp(const mcmp2_ctx *c) {
     hipError_t e = launch_x_lp(c, true);
     if (e != hipSuccess) return e;
     const int n_rt = (4 * c->nsp + LBM - 1) / LBM, n_ct = (c->E + LBM - 1) / LBM;
-    const int n_items = 2 * n_rt * n_ct;
-    spinor_lp_kernel<<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
+    spinor_lp_kernel<<<16 * ((n_rt * n_ct + 7) / 8), 256, 0, c->stream>>>(
         reinterpret_cast<const __bf16 *>(c->Cb), reinterpret_cast<const __bf16 *>(c->Xb), c->nsp, c->nLp,
         c->nbp - c->nLp, c->E, c->R, n_rt, n_ct, reinterpret_cast<float2 *>(c->psi));
     return hipGetLastError();
