@@ -52,33 +52,46 @@ __device__ inline _Float16 to_op<_Float16>(double v) {
     return (_Float16)v;
 }
 
-// grid (R / 64, ceil(nsp / 32), n_tau); psi float2 [nsp][R] -> U_t [R][Ktot]
+// (re, im) rounded to the operand type, packed into 32 bits (real part low)
+template <typename T>
+__device__ inline uint32_t pack_op(double re, double im) {
+    const T a = to_op<T>(re), b = to_op<T>(im);
+    return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+}
+
+// grid (R / 64, ceil(nsp / 32), ceil(n_tau / tpb)); psi float2 [nsp][R] ->
+// U_t [R][Ktot] for tpb tau samples per block from one LDS copy of the
+// block's psi tile (tpb = n_tau when the first two grid dimensions alone
+// give every CU several blocks, else 1).
 template <typename T>
 __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restrict__ psi,
                                                           const double *__restrict__ scale, int R, int nsp, int no,
-                                                          int Ko, int Ktot, T *__restrict__ U) {
+                                                          int Ko, int Ktot, int n_tau, int tpb, T *__restrict__ U) {
     __shared__ float2 tile[32][65];
     __shared__ double sq[32];
-    const int r0 = 64 * blockIdx.x, k0 = 32 * blockIdx.y, t = blockIdx.z;
+    const int r0 = 64 * blockIdx.x, k0 = 32 * blockIdx.y;
+    const int t_lo = tpb * (int)blockIdx.z, t_hi = min(n_tau, t_lo + tpb);
     const int tid = threadIdx.x;
-    if (tid < 32) {
-        const int k = k0 + tid;
-        sq[tid] = k < nsp ? sqrt(scale[(size_t)t * nsp + k]) : 0.0;
-    }
     for (int e = tid; e < 32 * 64; e += 256) {  // coalesced along rows
         const int kk = e >> 6, r = e & 63, k = k0 + kk;
         tile[kk][r] = k < nsp ? psi[(size_t)k * R + r0 + r] : float2{0.f, 0.f};
     }
-    __syncthreads();
-    T *Ut = U + (size_t)t * R * Ktot;
-    for (int e = tid; e < 32 * 64; e += 256) {  // coalesced along K within a row
-        const int r = e >> 5, kk = e & 31, k = k0 + kk;
-        if (k >= nsp) continue;
-        const int K = k < no ? 2 * k : Ko + 2 * (k - no);
-        const float2 v = tile[kk][r];
-        T *o = Ut + (size_t)(r0 + r) * Ktot + K;
-        o[0] = to_op<T>((double)v.x * sq[kk]);
-        o[1] = to_op<T>((double)v.y * sq[kk]);
+    for (int t = t_lo; t < t_hi; ++t) {
+        if (t > t_lo) __syncthreads();  // sq of the previous tau sample has been used
+        if (tid < 32) {
+            const int k = k0 + tid;
+            sq[tid] = k < nsp ? sqrt(scale[(size_t)t * nsp + k]) : 0.0;
+        }
+        __syncthreads();
+        T *Ut = U + (size_t)t * R * Ktot;
+        for (int e = tid; e < 32 * 64; e += 256) {  // coalesced along K within a row
+            const int r = e >> 5, kk = e & 31, k = k0 + kk;
+            if (k >= nsp) continue;
+            const int K = k < no ? 2 * k : Ko + 2 * (k - no);
+            const float2 v = tile[kk][r];
+            *reinterpret_cast<uint32_t *>(Ut + (size_t)(r0 + r) * Ktot + K) =
+                pack_op<T>((double)v.x * sq[kk], (double)v.y * sq[kk]);
+        }
     }
 }
 
@@ -409,9 +422,11 @@ hipError_t launch_big_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
 template <typename T>
 hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     T *U = reinterpret_cast<T *>(c->U);
-    dim3 g(c->R / 64, (c->nsp + 31) / 32, n_tau);
+    const int bx = c->R / 64, by = (c->nsp + 31) / 32;
+    const int tpb = bx * by >= 4 * c->n_cu ? n_tau : 1;
+    dim3 g(bx, by, (n_tau + tpb - 1) / tpb);
     lp_operands_kernel<T><<<g, 256, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->psi), c->scale, c->R,
-                                                    c->nsp, c->no, c->Ko, c->Ktot, U);
+                                                    c->nsp, c->no, c->Ko, c->Ktot, n_tau, tpb, U);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (sizeof(T) == 2)

@@ -83,7 +83,6 @@ struct mcmp2_ctx {
     Profiler prof;
 };
 
-// g(r) of Eq. basisSet; gpar[I] = (c1 N(z1), z1, c2 N(z2), z2).
 // Work items of the spinor GEMMs: (primitive set, spinor tile, point tile).
 // Block b runs on XCD b % 8; each XCD takes a contiguous range of the n_pairs
 // (spinor tile, point tile) pairs and first runs their small-component
@@ -99,6 +98,7 @@ __device__ inline bool spinor_set_item(int n_pairs, int &set, int &pair) {
     return true;
 }
 
+// g(r) of Eq. basisSet; gpar[I] = (c1 N(z1), z1, c2 N(z2), z2).
 __device__ inline double g_value(double x, double y, double z, const double *nuc, const double *gpar, int n_nuc) {
     double out = 0.0;
     for (int I = 0; I < n_nuc; ++I) {

@@ -119,12 +119,42 @@ __global__ void advance_kernel(double *__restrict__ walkers, double *__restrict_
 }
 
 // Neumaier step: (s, c) += x with the rounding error of s + x kept in c.
+__device__ inline void neumaier(double &s, double &c, double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
 __global__ void accumulate_kernel(const double *__restrict__ src, double *__restrict__ sum, double *__restrict__ comp,
                                   int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double s = sum[i], x = src[i], t = s + x;
-        comp[i] += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-        sum[i] = t;
+        double s = sum[i], c = comp[i];
+        neumaier(s, c, src[i]);
+        comp[i] = c;
+        sum[i] = s;
+    }
+}
+
+// The same steps on 16-byte aligned arrays, two doubles per access; the
+// last element of an odd n goes to thread 0.
+typedef double d2x __attribute__((ext_vector_type(2)));
+__global__ void accumulate2_kernel(const double *__restrict__ src, double *__restrict__ sum,
+                                   double *__restrict__ comp, int64_t n) {
+    const int64_t n2 = n / 2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+        const d2x x = reinterpret_cast<const d2x *>(src)[i];
+        d2x s = reinterpret_cast<const d2x *>(sum)[i], c = reinterpret_cast<const d2x *>(comp)[i];
+        double s0 = s[0], s1 = s[1], c0 = c[0], c1 = c[1];
+        neumaier(s0, c0, x[0]);
+        neumaier(s1, c1, x[1]);
+        reinterpret_cast<d2x *>(comp)[i] = d2x{c0, c1};
+        reinterpret_cast<d2x *>(sum)[i] = d2x{s0, s1};
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = sum[n - 1], c = comp[n - 1];
+        neumaier(s, c, src[n - 1]);
+        comp[n - 1] = c;
+        sum[n - 1] = s;
     }
 }
 
@@ -132,8 +162,15 @@ __global__ void accumulate_kernel(const double *__restrict__ src, double *__rest
 
 hipError_t launch_accumulate(const mcmp2_ctx *c, const double *src, double *sum, double *comp, int64_t n) {
     if (n == 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-    accumulate_kernel<<<(int)blocks, 256, 0, c->stream>>>(src, sum, comp, n);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(sum) |
+                           reinterpret_cast<uintptr_t>(comp)) & 15) == 0;
+    if (aligned) {
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n / 2 + 255) / 256, 4096));
+        accumulate2_kernel<<<(int)blocks, 256, 0, c->stream>>>(src, sum, comp, n);
+    } else {
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+        accumulate_kernel<<<(int)blocks, 256, 0, c->stream>>>(src, sum, comp, n);
+    }
     return hipGetLastError();
 }
 

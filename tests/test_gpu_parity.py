@@ -177,6 +177,22 @@ def test_accumulate_is_compensated():
     for i in range(5):
         ref = math.fsum(v[i] for v in steps)
         assert abs(got[i] - ref) <= 4 * np.spacing(abs(ref)) + 1e-300
+    # both kernel paths: 16-byte aligned arrays with an odd length (pairs plus
+    # a last element) and arrays offset by one double (element-wise path)
+    n = 1001
+    vals = [rng.standard_normal(n + 1) * 10.0 ** rng.integers(-8, 9, size=n + 1) for _ in range(60)]
+    for off in (0, 1):
+        sb = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+        cb = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+        for v in vals:
+            src = dev(v)  # referenced until the accumulation that reads it has finished
+            ctx.accumulate(src[off:off + n], sb[off:off + n], cb[off:off + n])
+            torch.cuda.synchronize()
+        got = (sb + cb).cpu().numpy()[off:off + n]
+        ref = np.array([math.fsum(v[off + i] for v in vals) for i in range(n)])
+        assert np.all(np.abs(got - ref) <= 4 * np.spacing(np.abs(ref)) + 1e-300)
+        untouched = 0 if off == 1 else n  # the element outside the view stays zero
+        assert float(sb[untouched].item()) == 0.0 and float(cb[untouched].item()) == 0.0
     # complex tensors are accumulated as interleaved doubles
     z = torch.zeros(3, dtype=torch.complex128, device="cuda")
     zc = torch.zeros(3, dtype=torch.complex128, device="cuda")
