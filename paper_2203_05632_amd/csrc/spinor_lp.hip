@@ -225,11 +225,16 @@ __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict
     }
 }
 
-// grad_coeffs[s][mu][k] (double2): rows mu of one set (XTb), columns r = 4 k + 2 s + ri (PBb[set])
+// grad_coeffs[s][mu][k] (double2): rows mu of one set (XTb), columns r = 4 k + 2 s + ri (PBb[set]).
+// The tile goes through LDS (rows of CGR floats: the 4-row steps of the
+// MFMA result layout fall in different banks) so that the stores run along
+// k: 32 consecutive complex values (512 B) per (s, mu).
+constexpr int CGR = 132;
 __global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restrict__ XTb, const __bf16 *__restrict__ PBb,
                                                            int nb, int nL, int nsp, int Ep, int n_rt_L, int n_rt_S,
                                                            int n_ct, double *__restrict__ grad_coeffs) {
-    __shared__ __align__(16) uint32_t lds[2 * 2 * LBM * LKW];
+    constexpr int MAIN = 2 * 2 * LBM * LKW, EPI = LBM * CGR;
+    __shared__ __align__(16) uint32_t lds[MAIN > EPI ? MAIN : EPI];
     const int n_items = (n_rt_L + n_rt_S) * n_ct;
     const int item = xcd_item(n_items);
     if (item >= n_items) return;
@@ -239,20 +244,26 @@ __global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restr
     const int mu0 = mu_lo + LBM * (set ? rt_all - n_rt_L : rt_all);
     f4v acc[4][4];
     lp_gemm_tile<__bf16>(XTb, Ep, mu0, mu_hi, PBb + (size_t)set * 4 * nsp * Ep, Ep, LBM * ct, 4 * nsp, Ep, lds, acc);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+    __syncthreads();  // the main loop's last LDS reads are done
+    float *tile = reinterpret_cast<float *>(lds);  // [mu - mu0][r - LBM ct]
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int r = LBM * ct + 64 * wc + 16 * j + li;
-        const int k = r >> 2, s = (r >> 1) & 1, ri = r & 1;
-        if (k >= nsp) continue;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int mu = mu0 + 64 * wr + 16 * i + 4 * lk + v;
-                if (mu < mu_hi) grad_coeffs[(((size_t)s * nb + mu) * nsp + k) * 2 + ri] = acc[i][j][v];
-            }
+            for (int v = 0; v < 4; ++v) tile[(64 * wr + 16 * i + 4 * lk + v) * CGR + 64 * wc + 16 * j + li] = acc[i][j][v];
+    __syncthreads();
+    // complex value e = tid + 256 q: row e / 64 of the tile, spin s = (e / 32) % 2, k = k0 + e % 32
+    const int k0 = (LBM * ct) / 4;
+    for (int q = 0; q < LBM * 64 / 256; ++q) {
+        const int e = tid + 256 * q, row = e >> 6, s = (e >> 5) & 1, kk = e & 31;
+        const int mu = mu0 + row, k = k0 + kk;
+        if (mu >= mu_hi || k >= nsp) continue;
+        const float *src = tile + row * CGR + 4 * kk + 2 * s;
+        *reinterpret_cast<double2 *>(grad_coeffs + (((size_t)s * nb + mu) * nsp + k) * 2) =
+            double2{(double)src[0], (double)src[1]};
     }
 }
 
