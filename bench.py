@@ -32,7 +32,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad", "accumulate"]
+PROFILED = ["spinor_gemm", "green_contract", "grad", "coef_grad"]
 HBM_PEAK_GBS = 8000.0   # published HBM3E bandwidth of one MI355X
 PROFILE_STEPS = 300   # steps of the HIP-event-timed pass after each throughput run
 # (operand precision, gradients[, interaction]); the interaction variants run the
@@ -101,9 +101,9 @@ def kernel_flops(inp) -> dict:
         "spinor_gemm": 16.0 * m * nsp * nb,          # 2m points x 4 components x nsp, real x complex over n_L or n_S
         "green_contract": green_flops(m, nsp, nt),
         "grad": 512.0 * m * (m - 1) * nsp * nt,      # Psibar = sum_t H_t Psi S_t, off-diagonal walker blocks
-        "coef_grad": 16.0 * m * nsp * nb,            # Cbar = X^T Psibar: same shape as the spinor GEMM
-        # compensated accumulation of both gradients per step: 5 doubles moved per element
-        "accumulate_bytes": 5 * 8.0 * (nsp + 2 * 2 * nb * nsp),
+        # Cbar = X^T Psibar: same shape as the spinor GEMM (its epilogue also adds the result
+        # to the compensated running sums over steps: 4 doubles moved per element)
+        "coef_grad": 16.0 * m * nsp * nb,
     }
 
 
@@ -124,11 +124,6 @@ def kernel_table(prof: dict, kflops: dict, K: int, prec: str) -> dict:
     out = {}
     for k, (tot_ms, _) in prof.items():
         avg_s = tot_ms / K / 1e3
-        if k == "accumulate":   # HBM-bound: reads src, sum, comp and writes sum, comp per element
-            gbs = kflops["accumulate_bytes"] / avg_s / 1e9
-            out[k] = {"us_per_step": round(avg_s * 1e6, 2), "GB_per_s": round(gbs, 1),
-                      "peak_frac": round(gbs / HBM_PEAK_GBS, 4)}
-            continue
         tf = kflops[k] / avg_s / 1e12
         op = operand_type(prec, k)
         out[k] = {"us_per_step": round(avg_s * 1e6, 2), "tflops": round(tf, 2), "operands": op,
@@ -182,18 +177,17 @@ def run_variant(inp, precision, grad, state, K, W, Kp, interaction="coulomb"):
     hist = torch.zeros((K, inp.n_tau, 3), dtype=torch.float64, device="cuda")
     scratch = torch.zeros((inp.n_tau, 3), dtype=torch.float64, device="cuda")
     g = {}
-    if grad:
-        g["eps"] = torch.zeros(inp.n_sp, dtype=torch.float64, device="cuda")
-        g["c"] = torch.zeros((2, inp.n_b, inp.n_sp), dtype=torch.complex128, device="cuda")
-        g["eps_s"], g["eps_c"] = torch.zeros_like(g["eps"]), torch.zeros_like(g["eps"])
-        g["c_s"], g["c_c"] = torch.zeros_like(g["c"]), torch.zeros_like(g["c"])
+    if grad:  # compensated running sums of both gradients over the steps
+        for k in ("eps_s", "eps_c"):
+            g[k] = torch.zeros(inp.n_sp, dtype=torch.float64, device="cuda")
+        for k in ("c_s", "c_c"):
+            g[k] = torch.zeros((2, inp.n_b, inp.n_sp), dtype=torch.complex128, device="cuda")
 
     def one(s, out):
         ctx.advance(wk, w, key, s, delta, tau)          # Metropolis move + tau samples (one launch)
         if grad:
-            ctx.step(wk, tau, out, grad_eps=g["eps"], grad_coeffs=g["c"])
-            ctx.accumulate(g["eps"], g["eps_s"], g["eps_c"])   # compensated sums over steps
-            ctx.accumulate(g["c"], g["c_s"], g["c_c"])
+            # estimator and both gradients, added to the running sums in the gradient kernels
+            ctx.step_accumulate(wk, tau, out, g["eps_s"], g["eps_c"], g["c_s"], g["c_c"])
         else:
             ctx.step(wk, tau, out)                      # estimator of Eq. redundant
 
@@ -207,7 +201,7 @@ def run_variant(inp, precision, grad, state, K, W, Kp, interaction="coulomb"):
     elapsed = time.perf_counter() - t0
     prof = {}
     if Kp > 0:
-        ctx.profile_begin(PROFILED, Kp * (len(PROFILED) + 2))  # accumulate runs twice per gradient step
+        ctx.profile_begin(PROFILED, Kp * (len(PROFILED) + 1))
         for i in range(Kp):
             one(step + W + K + i, scratch)
         prof = ctx.profile_end()

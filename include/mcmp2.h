@@ -128,6 +128,26 @@ int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t
                double *grad_eps, double *grad_coeffs);
 
 /*
+ * mcmp2_step_accumulate -- mcmp2_step with both gradients, each added to a
+ * running compensated sum instead of written out: the same step value and
+ * e2_out, and (eps_sum, eps_comp) and (coeffs_sum, coeffs_comp) end up
+ * bit for bit as after mcmp2_step followed by mcmp2_accumulate of grad_eps
+ * and of grad_coeffs (as 4 (n_L+n_S) n_sp doubles) into them, without the
+ * gradient arrays being written and read back (the accumulation of the
+ * gradient averages over MC steps, Eq. redundant).
+ *   walkers, tau, n_tau, e2_out : as for mcmp2_step.
+ *   eps_sum, eps_comp       : device [n_sp] doubles (compensated pair).
+ *   coeffs_sum, coeffs_comp : device complex [2][n_L+n_S][n_sp] (as
+ *                             grad_coeffs), 16-byte aligned.
+ * The caller zeroes the pairs to start; the running total of a gradient is
+ * sum + comp.
+ * Errors: EINVAL (null pointers, n_tau out of range, a non-Coulomb
+ * interaction), ESTATE (context without want_grad), EDEVICE.
+ */
+int mcmp2_step_accumulate(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
+                          double *eps_sum, double *eps_comp, double *coeffs_sum, double *coeffs_comp);
+
+/*
  * mcmp2_set_coefficients -- replace the context's spinor coefficients and
  * energies (Eq. (C), Eq. FinalMP2) with device arrays of the init layout:
  *   coeffs : device complex [2][n_L+n_S][n_sp];  eps : device [n_sp].

@@ -16,7 +16,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 INTERACTIONS = {"coulomb": 0, "gaunt": 1, "breit": 2}
 
 # Every symbol declared in include/mcmp2.h.
-EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_set_coefficients", "mcmp2_set_interaction", "mcmp2_pair_weights", "mcmp2_metropolis", "mcmp2_sample_tau",
+EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_step_accumulate", "mcmp2_set_coefficients", "mcmp2_set_interaction", "mcmp2_pair_weights", "mcmp2_metropolis", "mcmp2_sample_tau",
            "mcmp2_advance", "mcmp2_accumulate", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_destroy",
            "mcmp2_last_error"]
 KERNELS = ["walker_weights", "step_prep", "spinor_gemm", "green_contract", "reduce", "metropolis", "sample_tau",
@@ -59,6 +59,8 @@ def load() -> ctypes.CDLL:
     lib.mcmp2_init.restype = ctypes.c_int
     lib.mcmp2_step.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     lib.mcmp2_step.restype = ctypes.c_int
+    lib.mcmp2_step_accumulate.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.mcmp2_step_accumulate.restype = ctypes.c_int
     lib.mcmp2_set_coefficients.argtypes = [vp, vp, vp]
     lib.mcmp2_set_coefficients.restype = ctypes.c_int
     lib.mcmp2_set_interaction.argtypes = [vp, i32]

@@ -76,11 +76,10 @@ class Chain:
             self.w = torch.zeros(ctx.m, dtype=torch.float64, device=dev)
             self.tau = torch.zeros(self.n_tau, dtype=torch.float64, device=dev)
             self.n_acc = torch.zeros(1, dtype=torch.int32, device=dev)
-            if self.want_grad:
-                self.g_eps = torch.zeros(ctx.n_sp, dtype=torch.float64, device=dev)
-                self.g_c = torch.zeros((2, ctx.n_b, ctx.n_sp), dtype=torch.complex128, device=dev)
-                self.acc = {k: torch.zeros_like(v) for k, v in
-                            (("eps_s", self.g_eps), ("eps_c", self.g_eps), ("c_s", self.g_c), ("c_c", self.g_c))}
+            if self.want_grad:  # compensated running sums of both gradients
+                self.acc = {k: torch.zeros(ctx.n_sp, dtype=torch.float64, device=dev) for k in ("eps_s", "eps_c")}
+                self.acc.update({k: torch.zeros((2, ctx.n_b, ctx.n_sp), dtype=torch.complex128, device=dev)
+                                 for k in ("c_s", "c_c")})
         ctx.pair_weights(self.walkers, self.w)
 
     # -- sampling ---------------------------------------------------------------
@@ -118,9 +117,8 @@ class Chain:
             for i in range(nb):
                 ctx.advance(self.walkers, self.w, self.key, self.step, self.delta, self.tau)
                 if self.want_grad:
-                    ctx.step(self.walkers, self.tau, hist[i], grad_eps=self.g_eps, grad_coeffs=self.g_c)
-                    ctx.accumulate(self.g_eps, self.acc["eps_s"], self.acc["eps_c"])
-                    ctx.accumulate(self.g_c, self.acc["c_s"], self.acc["c_c"])
+                    ctx.step_accumulate(self.walkers, self.tau, hist[i], self.acc["eps_s"], self.acc["eps_c"],
+                                        self.acc["c_s"], self.acc["c_c"])
                 else:
                     ctx.step(self.walkers, self.tau, hist[i])
                 self.step += 1

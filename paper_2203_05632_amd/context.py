@@ -102,6 +102,22 @@ class Context:
                                                   name="grad_coeffs")))
         return e2_out
 
+    def step_accumulate(self, walkers: torch.Tensor, tau: torch.Tensor, e2_out: torch.Tensor,
+                        eps_sum: torch.Tensor, eps_comp: torch.Tensor, coeffs_sum: torch.Tensor,
+                        coeffs_comp: torch.Tensor) -> torch.Tensor:
+        """step() with both gradients added to compensated running sums
+        ((eps_sum, eps_comp): float64 [n_sp]; (coeffs_sum, coeffs_comp):
+        complex128 [2, n_b, n_sp]) instead of written out; bitwise the same as
+        step() followed by accumulate() of each gradient."""
+        n_tau = int(tau.shape[0])
+        check(self._lib.mcmp2_step_accumulate(
+            self._h, _dev(walkers, (self.m, 2, 3), name="walkers"), _dev(tau, (n_tau,), name="tau"), n_tau,
+            _dev(e2_out, (n_tau, 3), name="e2_out"), _dev(eps_sum, (self.n_sp,), name="eps_sum"),
+            _dev(eps_comp, (self.n_sp,), name="eps_comp"),
+            _dev(coeffs_sum, (2, self.n_b, self.n_sp), torch.complex128, name="coeffs_sum"),
+            _dev(coeffs_comp, (2, self.n_b, self.n_sp), torch.complex128, name="coeffs_comp")))
+        return e2_out
+
     def set_coefficients(self, coeffs: torch.Tensor = None, eps: torch.Tensor = None) -> None:
         """Replace the spinor coefficients / energies with device tensors (init layout)."""
         check(self._lib.mcmp2_set_coefficients(

@@ -40,7 +40,7 @@ void free_ctx(mcmp2_ctx *c) {
     void *bufs[] = {c->nuc, c->gpar, c->pgeo, c->pnl, c->coef, c->eps, c->hinv, c->rhat, c->psi,
                     c->scale, c->wtau, c->tiles, c->work, c->partial, c->XT,
                     c->Hm, c->Hp, c->psibar, c->eps_part, c->U, c->Vt, c->tiles16,
-                    c->Cb, c->Xb, c->XTb, c->PBb};
+                    c->Cb, c->Xb, c->XTb, c->PBb, c->gstage};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete c;
@@ -290,6 +290,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
         TRY(dalloc(&c->psibar, 2 * (size_t)nsp * c->R));
         TRY(dalloc(&c->eps_part, (size_t)(c->R / 32) * nsp));
         if (h16) TRY(dalloc(&c->Vt, (size_t)n_tau_max * nsp * c->R));
+        if (h16 && !coef_grad_lp_fused(c)) TRY(dalloc(&c->gstage, (size_t)((nsp + 1) & ~1) + 4 * (size_t)nb * nsp));
         // blocks that are never written (p = q, padding walkers) must read as zero
         TRY(check_hip(hipMemset(c->Hm, 0, hbytes), "hipMemset"));
         TRY(check_hip(hipMemset(c->Hp, 0, hbytes), "hipMemset"));
@@ -328,8 +329,9 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     return MCMP2_OK;
 }
 
-extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
-                          double *grad_eps, double *grad_coeffs) {
+// One step (Eq. redundant) with the gradients, if any, going to geps / gcoef.
+static int run_step(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
+                    grad_out geps, grad_out gcoef) {
     if (!c || !walkers || !tau || !e2_out) {
         set_error("null argument");
         return MCMP2_EINVAL;
@@ -338,7 +340,7 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
         set_error("n_tau=%d outside 1..%d", n_tau, c->n_tau_max);
         return MCMP2_EINVAL;
     }
-    const bool grad = grad_eps || grad_coeffs;
+    const bool grad = geps.any() || gcoef.any();
     if (grad && !c->want_grad) {
         set_error("gradient outputs requested but the context was created with want_grad = 0");
         return MCMP2_ESTATE;
@@ -361,10 +363,48 @@ extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau
     if ((rc = timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); })) != MCMP2_OK)
         return rc;
     if (!grad) return MCMP2_OK;
-    if ((rc = timed(c, MCMP2_K_GRAD, "adjoint", [&] { return launch_adjoint(c, tau, n_tau, grad_eps); })) != MCMP2_OK)
+    if ((rc = timed(c, MCMP2_K_GRAD, "adjoint", [&] { return launch_adjoint(c, tau, n_tau, geps); })) != MCMP2_OK)
         return rc;
-    if (!grad_coeffs) return MCMP2_OK;
-    return timed(c, MCMP2_K_COEF_GRAD, "coef_grad", [&] { return launch_coef_grad(c, grad_coeffs); });
+    if (!gcoef.any()) return MCMP2_OK;
+    return timed(c, MCMP2_K_COEF_GRAD, "coef_grad", [&] { return launch_coef_grad(c, gcoef); });
+}
+
+extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
+                          double *grad_eps, double *grad_coeffs) {
+    grad_out geps, gcoef;
+    geps.out = grad_eps;
+    gcoef.out = grad_coeffs;
+    return run_step(c, walkers, tau, n_tau, e2_out, geps, gcoef);
+}
+
+extern "C" int mcmp2_step_accumulate(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau,
+                                     double *e2_out, double *eps_sum, double *eps_comp, double *coeffs_sum,
+                                     double *coeffs_comp) {
+    if (!eps_sum || !eps_comp || !coeffs_sum || !coeffs_comp) {
+        set_error("null accumulator");
+        return MCMP2_EINVAL;
+    }
+    if (((reinterpret_cast<uintptr_t>(coeffs_sum) | reinterpret_cast<uintptr_t>(coeffs_comp)) & 15) != 0) {
+        set_error("coefficient accumulators must be 16-byte aligned (complex FP64)");
+        return MCMP2_EINVAL;
+    }
+    grad_out geps, gcoef;
+    if (c && c->gstage) {  // small BF16 / FP16 problems: gradients staged, then added
+        geps.out = c->gstage;
+        gcoef.out = c->gstage + ((c->nsp + 1) & ~1);
+        int rc = run_step(c, walkers, tau, n_tau, e2_out, geps, gcoef);
+        if (rc != MCMP2_OK) return rc;
+        if ((rc = timed(c, MCMP2_K_ACCUMULATE, "accumulate",
+                        [&] { return launch_accumulate(c, geps.out, eps_sum, eps_comp, c->nsp); })) != MCMP2_OK)
+            return rc;
+        return timed(c, MCMP2_K_ACCUMULATE, "accumulate",
+                     [&] { return launch_accumulate(c, gcoef.out, coeffs_sum, coeffs_comp, 4 * (int64_t)c->nb * c->nsp); });
+    }
+    geps.sum = eps_sum;
+    geps.comp = eps_comp;
+    gcoef.sum = coeffs_sum;
+    gcoef.comp = coeffs_comp;
+    return run_step(c, walkers, tau, n_tau, e2_out, geps, gcoef);
 }
 
 extern "C" int mcmp2_set_interaction(mcmp2_ctx *c, int32_t interaction) {

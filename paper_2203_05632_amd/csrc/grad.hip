@@ -145,15 +145,24 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
     }
 }
 
-// epsbar[k] = sum over row tiles of eps_part, in row-tile order.
+// epsbar[k] = sum over row tiles of eps_part, in row-tile order; written to
+// grad_eps or added to (sum, comp).
 __global__ void eps_reduce_kernel(const double *__restrict__ eps_part, int n_rowtiles, int nsp,
-                                  double *__restrict__ grad_eps) {
+                                  double *__restrict__ grad_eps, double *__restrict__ sum,
+                                  double *__restrict__ comp) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsp) return;
     double acc = 0.0;
 #pragma unroll 8  // loads of 8 row tiles in flight together; the adds keep their order
     for (int r = 0; r < n_rowtiles; ++r) acc += eps_part[(size_t)r * nsp + k];
-    grad_eps[k] = acc;
+    if (sum) {
+        double sv = sum[k], cv = comp[k];
+        neumaier(sv, cv, acc);
+        sum[k] = sv;
+        comp[k] = cv;
+    } else {
+        grad_eps[k] = acc;
+    }
 }
 
 // Cbar[s][mu][k] = sum_pt XT[mu][pt] psibar[k][4 pt + 2 set(mu) + s].
@@ -161,7 +170,8 @@ __global__ void eps_reduce_kernel(const double *__restrict__ eps_part, int n_row
 // split the point range, wave 0 adds the partial tiles in a fixed order.
 __global__ __launch_bounds__(256) void coef_grad_kernel(const double *__restrict__ XT, const double2 *__restrict__ psibar,
                                                         int E, int n_pts, int nb, int nL, int nsp, int R,
-                                                        int n_L_tiles, double2 *__restrict__ grad_coeffs) {
+                                                        int n_L_tiles, double2 *__restrict__ grad_coeffs,
+                                                        double2 *__restrict__ sum, double2 *__restrict__ comp) {
     __shared__ d4v red[3][4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -201,8 +211,21 @@ __global__ __launch_bounds__(256) void coef_grad_kernel(const double *__restrict
     for (int v = 0; v < 4; ++v) {
         const int mr = mu0 + 4 * v + lk;
         if (mr >= mu_hi) continue;
-        grad_coeffs[(size_t)mr * nsp + k] = double2{acc[0][v], acc[1][v]};                    // alpha
-        grad_coeffs[((size_t)nb + mr) * nsp + k] = double2{acc[2][v], acc[3][v]};             // beta
+        const size_t ia = (size_t)mr * nsp + k, ib = ((size_t)nb + mr) * nsp + k;  // alpha, beta
+        if (sum) {
+            double2 sa = sum[ia], ca = comp[ia], sb = sum[ib], cb = comp[ib];
+            neumaier(sa.x, ca.x, acc[0][v]);
+            neumaier(sa.y, ca.y, acc[1][v]);
+            neumaier(sb.x, cb.x, acc[2][v]);
+            neumaier(sb.y, cb.y, acc[3][v]);
+            sum[ia] = sa;
+            comp[ia] = ca;
+            sum[ib] = sb;
+            comp[ib] = cb;
+        } else {
+            grad_coeffs[ia] = double2{acc[0][v], acc[1][v]};
+            grad_coeffs[ib] = double2{acc[2][v], acc[3][v]};
+        }
     }
 }
 
@@ -229,7 +252,7 @@ hipError_t launch_grad_gemm(const mcmp2_ctx *c, const double *tau, int n_tau, in
 
 }  // namespace
 
-hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps) {
+hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, grad_out grad_eps) {
     const int n_occ_tiles = (c->no + 31) / 32, n_vir_tiles = (c->nsp - c->no + 31) / 32;
     const bool h16 = c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16;
     const int n_rowtiles = h16 ? adjoint_lp_row_tiles(c) : c->R / 32;
@@ -239,22 +262,25 @@ hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, doub
                                                  : launch_grad_gemm<float2>(c, tau, n_tau, n_occ_tiles, n_vir_tiles);
         if (e != hipSuccess) return e;
     }
-    if (grad_eps) {
-        eps_reduce_kernel<<<(c->nsp + 255) / 256, 256, 0, c->stream>>>(c->eps_part, n_rowtiles, c->nsp, grad_eps);
+    if (grad_eps.any()) {
+        eps_reduce_kernel<<<(c->nsp + 255) / 256, 256, 0, c->stream>>>(c->eps_part, n_rowtiles, c->nsp, grad_eps.out,
+                                                                       grad_eps.sum, grad_eps.comp);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_coef_grad(const mcmp2_ctx *c, double *grad_coeffs) {
+hipError_t launch_coef_grad(const mcmp2_ctx *c, grad_out grad_coeffs) {
     if (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) return launch_coef_grad_lp(c, grad_coeffs);
     const double2 *psibar = reinterpret_cast<const double2 *>(c->psibar);
     {
         const int n_L_tiles = (c->nL + 15) / 16, n_S_tiles = (c->nS + 15) / 16;
         dim3 g2(n_L_tiles + n_S_tiles, (c->nsp + 15) / 16);
         coef_grad_kernel<<<g2, 256, 0, c->stream>>>(c->XT, psibar, c->E, 2 * c->m, c->nb, c->nL, c->nsp, c->R,
-                                                    n_L_tiles, reinterpret_cast<double2 *>(grad_coeffs));
+                                                    n_L_tiles, reinterpret_cast<double2 *>(grad_coeffs.out),
+                                                    reinterpret_cast<double2 *>(grad_coeffs.sum),
+                                                    reinterpret_cast<double2 *>(grad_coeffs.comp));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -79,8 +79,26 @@ struct mcmp2_ctx {
     void *XTb = nullptr;  // [nb][Ep] basis values per primitive (gradients)
     void *PBb = nullptr;  // [2 sets][4 nsp][Ep] psi gradient (gradients)
     double *eps_part = nullptr; // [row tiles][nsp] eps-gradient partials (32-row tiles, or 128-row in BF16 / FP16 modes)
+    // BF16 / FP16 modes below one coefficient-gradient tile per two CUs: staging
+    // of both gradients for mcmp2_step_accumulate ([nsp] rounded up to even,
+    // then complex [2][nb][nsp]), which there adds them with separate launches
+    double *gstage = nullptr;
 
     Profiler prof;
+};
+
+// Neumaier step: (s, c) += x with the rounding error of s + x kept in c.
+__device__ inline void neumaier(double &s, double &c, double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+// Where a gradient goes: written to out, or (when sum is set) added to the
+// compensated pair (sum, comp) element by element with neumaier().
+struct grad_out {
+    double *out = nullptr, *sum = nullptr, *comp = nullptr;
+    bool any() const { return out || sum; }
 };
 
 // Work items of the spinor GEMMs: (primitive set, spinor tile, point tile).
@@ -136,8 +154,8 @@ hipError_t launch_green_lp(const mcmp2_ctx *c, int n_tau, bool grad);
 bool green_big_selected(const mcmp2_ctx *c, int n_tau);
 void build_big_tiles(int T16, std::vector<int> &tiles);
 hipError_t launch_accumulate(const mcmp2_ctx *c, const double *src, double *sum, double *comp, int64_t n);
-hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, double *grad_eps);
-hipError_t launch_coef_grad(const mcmp2_ctx *c, double *grad_coeffs);
+hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, grad_out grad_eps);
+hipError_t launch_coef_grad(const mcmp2_ctx *c, grad_out grad_coeffs);
 hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau);
 hipError_t launch_coef_lp(const mcmp2_ctx *c);
 hipError_t launch_spinor_lp(const mcmp2_ctx *c);
@@ -145,6 +163,8 @@ hipError_t launch_spinor_lp(const mcmp2_ctx *c);
 bool spinor_lp_tiled(const mcmp2_ctx *c);
 // XT -> XTb (gradients) and, with want_xb, the split-BF16 operand Xb
 hipError_t launch_x_lp(const mcmp2_ctx *c, bool want_xb);
-hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, double *grad_coeffs);
+hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, grad_out grad_coeffs);
+// whether the BF16 coefficient gradient adds into running sums itself (enough tiles to hide its loads)
+bool coef_grad_lp_fused(const mcmp2_ctx *c);
 int adjoint_lp_row_tiles(const mcmp2_ctx *c);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);

@@ -118,13 +118,7 @@ __global__ void advance_kernel(double *__restrict__ walkers, double *__restrict_
         tau[i - m] = tau_value(i - m, key0, key1, step, lambda);
 }
 
-// Neumaier step: (s, c) += x with the rounding error of s + x kept in c.
-__device__ inline void neumaier(double &s, double &c, double x) {
-    const double t = s + x;
-    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-    s = t;
-}
-
+// Compensated accumulation with neumaier() (internal.hpp).
 __global__ void accumulate_kernel(const double *__restrict__ src, double *__restrict__ sum, double *__restrict__ comp,
                                   int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {

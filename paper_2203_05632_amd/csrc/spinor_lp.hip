@@ -232,7 +232,8 @@ __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict
 constexpr int CGR = 132;
 __global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restrict__ XTb, const __bf16 *__restrict__ PBb,
                                                            int nb, int nL, int nsp, int Ep, int n_rt_L, int n_rt_S,
-                                                           int n_ct, double *__restrict__ grad_coeffs) {
+                                                           int n_ct, double *__restrict__ grad_coeffs,
+                                                           double *__restrict__ sum, double *__restrict__ comp) {
     constexpr int MAIN = 2 * 2 * LBM * LKW, EPI = LBM * CGR;
     __shared__ __align__(16) uint32_t lds[MAIN > EPI ? MAIN : EPI];
     const int n_items = (n_rt_L + n_rt_S) * n_ct;
@@ -258,12 +259,20 @@ __global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restr
     // complex value e = tid + 256 q: row e / 64 of the tile, spin s = (e / 32) % 2, k = k0 + e % 32
     const int k0 = (LBM * ct) / 4;
     for (int q = 0; q < LBM * 64 / 256; ++q) {
-        const int e = tid + 256 * q, row = e >> 6, s = (e >> 5) & 1, kk = e & 31;
+        const int e = tid + 256 * q, row = e >> 6, sp = (e >> 5) & 1, kk = e & 31;
         const int mu = mu0 + row, k = k0 + kk;
         if (mu >= mu_hi || k >= nsp) continue;
-        const float *src = tile + row * CGR + 4 * kk + 2 * s;
-        *reinterpret_cast<double2 *>(grad_coeffs + (((size_t)s * nb + mu) * nsp + k) * 2) =
-            double2{(double)src[0], (double)src[1]};
+        const float *src = tile + row * CGR + 4 * kk + 2 * sp;
+        const size_t o = (((size_t)sp * nb + mu) * nsp + k) * 2;
+        if (sum) {  // compensated accumulation instead of the store
+            double2 sv = *reinterpret_cast<const double2 *>(sum + o), cv = *reinterpret_cast<const double2 *>(comp + o);
+            neumaier(sv.x, cv.x, (double)src[0]);
+            neumaier(sv.y, cv.y, (double)src[1]);
+            *reinterpret_cast<double2 *>(sum + o) = sv;
+            *reinterpret_cast<double2 *>(comp + o) = cv;
+        } else {
+            *reinterpret_cast<double2 *>(grad_coeffs + o) = double2{(double)src[0], (double)src[1]};
+        }
     }
 }
 
@@ -303,7 +312,16 @@ hipError_t launch_spinor_lp(const mcmp2_ctx *c) {
     return hipGetLastError();
 }
 
-hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, double *grad_coeffs) {
+// The fused accumulation reads and rewrites the running sums in the epilogue;
+// with fewer than two tiles per CU those dependent loads are not hidden (340
+// spinors: 66 tiles, 23 us against 8 us plus two 5 us accumulation launches).
+bool coef_grad_lp_fused(const mcmp2_ctx *c) {
+    const int n_rt_L = (c->nL + LBM - 1) / LBM, n_rt_S = (c->nS + LBM - 1) / LBM;
+    const int n_ct = (4 * c->nsp + LBM - 1) / LBM;
+    return (n_rt_L + n_rt_S) * n_ct >= 2 * c->n_cu;
+}
+
+hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, grad_out grad_coeffs) {
     dim3 g1((c->E + 255) / 256, c->nsp);
     psibar_lp_kernel<<<g1, 256, 0, c->stream>>>(reinterpret_cast<const double2 *>(c->psibar), c->nsp, c->R, c->E,
                                                 c->Ep, reinterpret_cast<__bf16 *>(c->PBb));
@@ -314,6 +332,6 @@ hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, double *grad_coeffs) {
     const int n_items = (n_rt_L + n_rt_S) * n_ct;
     coef_grad_lp_kernel<<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
         reinterpret_cast<const __bf16 *>(c->XTb), reinterpret_cast<const __bf16 *>(c->PBb), c->nb, c->nL, c->nsp,
-        c->Ep, n_rt_L, n_rt_S, n_ct, grad_coeffs);
+        c->Ep, n_rt_L, n_rt_S, n_ct, grad_coeffs.out, grad_coeffs.sum, grad_coeffs.comp);
     return hipGetLastError();
 }

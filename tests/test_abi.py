@@ -46,3 +46,15 @@ def test_set_interaction_rejects_null_context():
     from paper_2203_05632_amd import load
     lib = load()
     assert lib.mcmp2_set_interaction(None, 2) == -1 and b"null" in lib.mcmp2_last_error()
+
+
+def test_step_accumulate_validates_before_touching_device():
+    from paper_2203_05632_amd import load
+    lib = load()
+    p16 = ctypes.c_void_p(16)
+    assert lib.mcmp2_step_accumulate(None, p16, p16, 1, p16, None, p16, p16, p16) == -1
+    assert b"null accumulator" in lib.mcmp2_last_error()
+    assert lib.mcmp2_step_accumulate(None, p16, p16, 1, p16, p16, p16, ctypes.c_void_p(24), p16) == -1
+    assert b"16-byte aligned" in lib.mcmp2_last_error()
+    assert lib.mcmp2_step_accumulate(None, p16, p16, 1, p16, p16, p16, p16, p16) == -1
+    assert b"null argument" in lib.mcmp2_last_error()
