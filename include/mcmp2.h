@@ -91,10 +91,12 @@ typedef struct {
  *                exp(+-eps tau) scalings (applied as square roots to both
  *                Green's-function operands, rounded once), pair weights and
  *                every sum stay in FP64.
- *   want_grad  : non-zero to allow gradient outputs in mcmp2_step; allocates
- *                2 n_tau_max (8 m_pad)^2 complex adjoint matrices (FP64, or
- *                packed BF16 pairs in the BF16 / FP16 modes; m_pad = m
- *                rounded up to a multiple of 8).
+ *   want_grad  : non-zero to allow gradient outputs in mcmp2_step and
+ *                mcmp2_step_accumulate; allocates 2 n_tau_max (8 m_pad)^2
+ *                complex adjoint matrices (FP64, or packed BF16 pairs in the
+ *                BF16 / FP16 modes; m_pad = m rounded up to a multiple of 8)
+ *                and, in the BF16 / FP16 modes of small problems, a staging
+ *                copy of both gradients.
  *   hip_stream : hipStream_t to enqueue on (NULL = default stream).
  *   out        : receives the context.
  * lambda = 2 (eps_LUMO - eps_HOMO) (Eq. tauWeight and the rule after it) and
