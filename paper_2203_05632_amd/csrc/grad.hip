@@ -229,6 +229,118 @@ __global__ __launch_bounds__(256) void coef_grad_kernel(const double *__restrict
     }
 }
 
+// Large problems: 64 mu x 64 k output tiles (4 waves of 32 x 32, each 2 x 2
+// MFMA sub-tiles for the four components alpha re, alpha im, beta re, beta
+// im), points in chunks of CGK through LDS (double-buffered, the next chunk
+// prefetched into registers): As[pt][mu] from XT, Bs[pt][component][k] from
+// psibar.  Rows are padded by two doubles so that the four 128-byte row
+// segments of one MFMA operand read fall in different banks.  Work items
+// (mu tile, k tile), mu-tile major, are dealt to the XCDs in contiguous ranges
+// (block b runs on XCD b % 8): blocks sharing XT rows read them through one L2.
+constexpr int CGK = 8;        // points per chunk
+constexpr int CGT = 64;       // mu and k per block tile
+constexpr int CGP = CGT + 2;  // padded LDS row (doubles)
+
+__global__ __launch_bounds__(256) void coef_grad_tile_kernel(const double *__restrict__ XT,
+                                                             const double2 *__restrict__ psibar, int E, int n_pts,
+                                                             int nb, int nL, int nsp, int R, int n_L_tiles,
+                                                             int n_k_tiles, int n_items,
+                                                             double2 *__restrict__ grad_coeffs,
+                                                             double2 *__restrict__ sum, double2 *__restrict__ comp) {
+    __shared__ __align__(16) double As[2][CGK][CGP];
+    __shared__ __align__(16) double Bs[2][CGK][4][CGP];
+    const int per = (n_items + 7) / 8;
+    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= n_items) return;
+    const int mt = item / n_k_tiles, kt = item % n_k_tiles;
+    const bool setL = mt < n_L_tiles;
+    const int mu0 = setL ? CGT * mt : nL + CGT * (mt - n_L_tiles);
+    const int mu_hi = setL ? nL : nb;
+    const int cbase = setL ? 0 : 2;  // psibar index 4 pt + 2 set + s
+    const int k0 = CGT * kt;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wk = wave & 1, li = lane & 15, lk = lane >> 4;
+
+    // staging: A element e = tid + 256 j (j < 2): mu e / 8, point e % 8;
+    //          B pair e = tid + 256 j (j < 4): k e / 16, point (e / 2) % 8, spin e % 2
+    double ra[2];
+    double2 rb[4];
+    auto gload = [&](int p0) __attribute__((always_inline)) {
+        for (int j = 0; j < 2; ++j) {
+            const int e = tid + 256 * j, mu = mu0 + e / 8, pt = p0 + e % 8;
+            ra[j] = (mu < mu_hi && pt < n_pts) ? XT[(size_t)mu * E + pt] : 0.0;
+        }
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + 256 * j, k = k0 + e / 16, pt = p0 + (e / 2) % 8, sp = e % 2;
+            rb[j] = (k < nsp && pt < n_pts) ? psibar[(size_t)k * R + 4 * pt + cbase + sp] : double2{0.0, 0.0};
+        }
+    };
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+        for (int j = 0; j < 2; ++j) {
+            const int e = tid + 256 * j;
+            As[buf][e % 8][e / 8] = ra[j];
+        }
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + 256 * j, kl = e / 16, pl = (e / 2) % 8, sp = e % 2;
+            Bs[buf][pl][2 * sp][kl] = rb[j].x;
+            Bs[buf][pl][2 * sp + 1][kl] = rb[j].y;
+        }
+    };
+    d4v acc[2][2][4];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int c = 0; c < 4; ++c) acc[i][j][c] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int n_chunks = (n_pts + CGK - 1) / CGK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < n_chunks; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < n_chunks) gload(CGK * (ch + 1));
+#pragma unroll
+        for (int ks = 0; ks < CGK; ks += 4) {
+            double a[2], b[2][4];
+            for (int i = 0; i < 2; ++i) a[i] = As[buf][ks + lk][32 * wm + 16 * i + li];
+            for (int j = 0; j < 2; ++j)
+                for (int c = 0; c < 4; ++c) b[j][c] = Bs[buf][ks + lk][c][32 * wk + 16 * j + li];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    for (int c = 0; c < 4; ++c)
+                        acc[i][j][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j][c], acc[i][j][c], 0, 0, 0);
+        }
+        if (ch + 1 < n_chunks) lstore(buf ^ 1);
+        __syncthreads();
+    }
+    // result element v of sub-tile (i, j): mu = mu0 + 32 wm + 16 i + 4 v + lk, k = k0 + 32 wk + 16 j + li
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = k0 + 32 * wk + 16 * j + li;
+            if (k >= nsp) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int mr = mu0 + 32 * wm + 16 * i + 4 * v + lk;
+                if (mr >= mu_hi) continue;
+                const size_t ia = (size_t)mr * nsp + k, ib = ((size_t)nb + mr) * nsp + k;  // alpha, beta
+                if (sum) {
+                    double2 sa = sum[ia], ca = comp[ia], sb = sum[ib], cb = comp[ib];
+                    neumaier(sa.x, ca.x, acc[i][j][0][v]);
+                    neumaier(sa.y, ca.y, acc[i][j][1][v]);
+                    neumaier(sb.x, cb.x, acc[i][j][2][v]);
+                    neumaier(sb.y, cb.y, acc[i][j][3][v]);
+                    sum[ia] = sa;
+                    comp[ia] = ca;
+                    sum[ib] = sb;
+                    comp[ib] = cb;
+                } else {
+                    grad_coeffs[ia] = double2{acc[i][j][0][v], acc[i][j][1][v]};
+                    grad_coeffs[ib] = double2{acc[i][j][2][v], acc[i][j][3][v]};
+                }
+            }
+        }
+}
+
 template <typename P>
 hipError_t launch_grad_gemm(const mcmp2_ctx *c, const double *tau, int n_tau, int n_occ_tiles, int n_vir_tiles) {
     const double2 *Hm = reinterpret_cast<const double2 *>(c->Hm), *Hp = reinterpret_cast<const double2 *>(c->Hp);
@@ -274,6 +386,15 @@ hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, grad
 hipError_t launch_coef_grad(const mcmp2_ctx *c, grad_out grad_coeffs) {
     if (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) return launch_coef_grad_lp(c, grad_coeffs);
     const double2 *psibar = reinterpret_cast<const double2 *>(c->psibar);
+    const int n_tL = (c->nL + CGT - 1) / CGT, n_tS = (c->nS + CGT - 1) / CGT, n_tk = (c->nsp + CGT - 1) / CGT;
+    const int n_items = (n_tL + n_tS) * n_tk;
+    if (n_items >= 2 * c->n_cu) {  // 64 x 64 tiles once every CU gets two
+        coef_grad_tile_kernel<<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
+            c->XT, psibar, c->E, 2 * c->m, c->nb, c->nL, c->nsp, c->R, n_tL, n_tk, n_items,
+            reinterpret_cast<double2 *>(grad_coeffs.out), reinterpret_cast<double2 *>(grad_coeffs.sum),
+            reinterpret_cast<double2 *>(grad_coeffs.comp));
+        return hipGetLastError();
+    }
     {
         const int n_L_tiles = (c->nL + 15) / 16, n_S_tiles = (c->nS + 15) / 16;
         dim3 g2(n_L_tiles + n_S_tiles, (c->nsp + 15) / 16);

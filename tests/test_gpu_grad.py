@@ -40,6 +40,8 @@ CASES = [
     ("C0", dict(n_tau=2), [0.3, 1.1]),
     ("C0", dict(m=13, n_occ=6, n_vir=10, n_tau=3), [0.2, 0.7, 2.5]),   # ragged tiles, odd tau count
     ("C1", dict(), [0.17, 0.83]),
+    # 980 spinors, 600 + 1380 primitives: 512 tiles of 64 x 64, the tiled coefficient-gradient kernel
+    ("C3", dict(m=16, n_tau=1), [0.4]),
 ]
 
 
