@@ -116,6 +116,9 @@ int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps
  *   e2_out  : device [n_tau][3]: per tau, the direct part Re(-D/2 ...), the
  *             exchange part Re(+X/2 ...) and their sum, each divided by
  *             w_p w_q w(tau) and averaged over the mC2 pairs p < q.
+ *   value   : device [1] or NULL: the step value
+ *             V = (1/n_tau) sum_t e2_out[t][2] (tau samples averaged at the
+ *             same walkers), summed in tau order with compensation.
  *   grad_eps    : device [n_sp] or NULL.  dV/d eps_k of the step value
  *                 V = (1/n_tau) sum_t e2_out[t][2], at fixed walkers, tau and
  *                 lambda (lambda is a sampling parameter frozen at init).
@@ -127,7 +130,7 @@ int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps
  * non-Coulomb interaction), ESTATE, EDEVICE.
  */
 int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
-               double *grad_eps, double *grad_coeffs);
+               double *value, double *grad_eps, double *grad_coeffs);
 
 /*
  * mcmp2_step_accumulate -- mcmp2_step with both gradients, each added to a
@@ -246,7 +249,9 @@ int mcmp2_constants(const mcmp2_ctx *ctx, double *lambda, double *n_g);
  * measurement harnesses.  mcmp2_profile_begin(ctx, mask, max_launches)
  * starts recording a start/stop event pair around every launch of the
  * kernels selected by `mask` (bit i = kernel id i below), for at most
- * max_launches launches in total (later launches run untimed).
+ * max_launches launches in total (later launches run untimed).  Ids 0-10
+ * time a stage of a call (which may enqueue several kernels); ids 11-12
+ * time each dispatch of one kernel, so their launch counts are dispatches.
  * mcmp2_profile_end synchronises the stream, writes per-kernel total
  * milliseconds and launch counts into host arrays of length MCMP2_NKERNELS
  * (either may be NULL) and stops recording.
@@ -264,7 +269,10 @@ enum {
     MCMP2_K_GRAD = 8,           /* adjoint GEMM: psi and eps gradients */
     MCMP2_K_ACCUMULATE = 9,     /* mcmp2_accumulate */
     MCMP2_K_COEF_GRAD = 10,     /* coefficient gradient from the psi gradient */
-    MCMP2_NKERNELS = 11
+    /* single dispatches inside the stages above (one pair per dispatch) */
+    MCMP2_K_GREEN_GEMM = 11,    /* the Green's-function GEMM + contraction kernel itself */
+    MCMP2_K_ADJ_GEMM = 12,      /* the adjoint GEMM kernel itself */
+    MCMP2_NKERNELS = 13
 };
 int mcmp2_profile_begin(mcmp2_ctx *ctx, uint32_t mask, int32_t max_launches);
 int mcmp2_profile_end(mcmp2_ctx *ctx, double *total_ms, int64_t *launches);

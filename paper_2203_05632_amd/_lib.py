@@ -20,7 +20,7 @@ EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_step_accumulate", "mcmp2_set_coeff
            "mcmp2_advance", "mcmp2_accumulate", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_destroy",
            "mcmp2_last_error"]
 KERNELS = ["walker_weights", "step_prep", "spinor_gemm", "green_contract", "reduce", "metropolis", "sample_tau",
-           "advance", "grad", "accumulate", "coef_grad"]
+           "advance", "grad", "accumulate", "coef_grad", "green_gemm", "adj_gemm"]
 
 
 class Basis(ctypes.Structure):
@@ -57,7 +57,7 @@ def load() -> ctypes.CDLL:
     lib.mcmp2_init.argtypes = [ctypes.POINTER(Basis), vp, vp, i32, i32, i32, i32, i32, i32, vp,
                                ctypes.POINTER(vp)]
     lib.mcmp2_init.restype = ctypes.c_int
-    lib.mcmp2_step.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.mcmp2_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.mcmp2_step.restype = ctypes.c_int
     lib.mcmp2_step_accumulate.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.mcmp2_step_accumulate.restype = ctypes.c_int

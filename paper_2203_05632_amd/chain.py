@@ -1,19 +1,37 @@
 """One Markov chain of the stochastic MP2 method on the GPU, with burn-in,
-blocking statistics, checkpoint / resume and the merge of independent chains
-(Sec. III of the paper: each processor runs its own chain and the results are
-combined as weighted averages at the end).
+blocking statistics, periodic records, checkpoint / resume and the merge of
+independent chains (Sec. III of the paper: each processor runs its own chain,
+periodically records how many steps it has done with the running mean and
+its statistical uncertainty, so that a job killed at any time loses nothing,
+and the results are combined as weighted averages at the end).
 
 Every random number of a chain comes from the counter-based generator of the
 library (key = (seed, chain), counter = step), and every kernel sums in a
 fixed order, so a chain resumed from a checkpoint continues bit for bit as if
 it had never stopped.  Chains on separate HIP streams of one GPU run
 concurrently and independently.
+
+Run directory (``Chain(..., run_dir=...)``):
+  records.jsonl           one JSON record per block of steps: N (post-burn-in
+                          steps so far), step (counter of the next move),
+                          I_N and sigma_bar_N of the direct / exchange / total
+                          parts, the block's acceptance ratio and steps/s;
+  chain-<step>.npz        checkpoints, written to a temporary file, flushed to
+                          disk and renamed into place, so a checkpoint file is
+                          either complete or absent; the newest two are kept.
+``Chain.resume(ctx, run_dir)`` continues from the newest checkpoint that
+loads completely (a torn temporary file or a damaged newer file is skipped)
+and drops the records written after it.
 """
 from __future__ import annotations
 
+import glob
+import json
 import math
+import os
+import time
 from dataclasses import dataclass
-from typing import Sequence
+from typing import Optional, Sequence
 
 import numpy as np
 import torch
@@ -56,12 +74,93 @@ def merge(results: Sequence[ChainResult]) -> ChainResult:
     return ChainResult(int(n.sum()), mean, sigma, ge, gc)
 
 
+CHECKPOINT_FORMAT = 2
+_CKPT_KEYS = ("format", "walkers", "w", "key", "step", "n_burn", "delta", "n_tau", "values", "want_grad",
+              "accepted", "proposed")
+
+
+def atomic_savez(path: str, **arrays) -> None:
+    """np.savez to `path` so that `path` is either the complete new file or
+    untouched: write a temporary file in the same directory, flush it to
+    disk, rename it over `path`, then flush the directory entry."""
+    d = os.path.dirname(os.path.abspath(path))
+    tmp = os.path.join(d, f".{os.path.basename(path)}.{os.getpid()}.tmp")
+    with open(tmp, "wb") as fh:
+        np.savez(fh, **arrays)
+        fh.flush()
+        os.fsync(fh.fileno())
+    os.replace(tmp, path)
+    fd = os.open(d, os.O_RDONLY)
+    try:
+        os.fsync(fd)
+    finally:
+        os.close(fd)
+
+
+def read_checkpoint(path: str) -> Optional[dict]:
+    """The arrays of a chain checkpoint, or None if the file is missing,
+    truncated, of another format or lacks a field."""
+    try:
+        with np.load(path, allow_pickle=False) as z:
+            st = {k: z[k] for k in z.files}
+    except Exception:
+        return None
+    if any(k not in st for k in _CKPT_KEYS) or int(st["format"]) != CHECKPOINT_FORMAT:
+        return None
+    if bool(st["want_grad"]) and any("acc_" + k not in st for k in ("eps_s", "eps_c", "c_s", "c_c")):
+        return None
+    return st
+
+
+def checkpoint_path(run_dir: str, step: int) -> str:
+    return os.path.join(run_dir, f"chain-{step:012d}.npz")
+
+
+def latest_checkpoint(run_dir: str) -> Optional[str]:
+    """Newest checkpoint of a run directory that loads completely."""
+    for path in sorted(glob.glob(os.path.join(run_dir, "chain-*.npz")), reverse=True):
+        if read_checkpoint(path) is not None:
+            return path
+    return None
+
+
+def read_records(run_dir: str) -> list:
+    """The block records of a run directory (a torn last line is ignored)."""
+    out = []
+    try:
+        with open(os.path.join(run_dir, "records.jsonl")) as fh:
+            for line in fh:
+                try:
+                    out.append(json.loads(line))
+                except ValueError:
+                    break
+    except FileNotFoundError:
+        pass
+    return out
+
+
+def truncate_records(run_dir: str, n_steps: int) -> None:
+    """Keep the records up to N = n_steps (those a checkpoint covers),
+    rewriting the file atomically."""
+    keep = [r for r in read_records(run_dir) if r["N"] <= n_steps]
+    path = os.path.join(run_dir, "records.jsonl")
+    tmp = os.path.join(run_dir, f".records.jsonl.{os.getpid()}.tmp")
+    with open(tmp, "w") as fh:
+        for r in keep:
+            fh.write(json.dumps(r) + "\n")
+        fh.flush()
+        os.fsync(fh.fileno())
+    os.replace(tmp, path)
+
+
 class Chain:
     """A chain over one Context.  walkers0: initial positions [m][2][3]
-    (bohr, host or device); key = (seed, chain) of the generator."""
+    (bohr, host or device); key = (seed, chain) of the generator.  With
+    run_dir, run() appends one record per block to run_dir/records.jsonl and
+    writes a checkpoint every `checkpoint_every` blocks (0: never)."""
 
     def __init__(self, ctx: Context, walkers0, key=(0, 0), delta: float = 0.5, n_tau: int = None,
-                 want_grad: bool = False):
+                 want_grad: bool = False, run_dir: str = None, checkpoint_every: int = 1):
         self.ctx = ctx
         self.key = (int(key[0]), int(key[1]))
         self.delta = float(delta)
@@ -70,6 +169,13 @@ class Chain:
         self.step = 0          # counter of the next Metropolis move
         self.n_burn = 0        # moves spent in burn-in
         self.values = []       # host blocks of per-step [direct, exchange, total] (tau-averaged)
+        self.accepted = 0      # accepted / proposed moves after burn-in
+        self.proposed = 0
+        self.run_dir = run_dir
+        self.checkpoint_every = int(checkpoint_every)
+        self._blocks = 0
+        if run_dir is not None:
+            os.makedirs(run_dir, exist_ok=True)
         dev = torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.stream(ctx.stream):
             self.walkers = torch.as_tensor(np.asarray(walkers0, dtype=np.float64), device=dev).contiguous().clone()
@@ -104,18 +210,21 @@ class Chain:
             self.delta *= 1.1 if acc > target else 0.9
         self.n_burn = self.step
 
-    def run(self, n_steps: int, block: int = 1000):
+    def run(self, n_steps: int, block: int = 100):
         """n_steps MC steps (move, tau samples, estimator and, with gradients,
         the adjoint and its compensated accumulation); per-step values are
-        copied to the host every `block` steps."""
+        copied to the host every `block` steps (N_b = 100 by default), when
+        the block's record and, on schedule, a checkpoint are written."""
         ctx = self.ctx
         done = 0
         while done < n_steps:
             nb = min(block, n_steps - done)
+            t0 = time.perf_counter()
             with torch.cuda.stream(ctx.stream):
                 hist = torch.empty((nb, self.n_tau, 3), dtype=torch.float64, device=self.w.device)
+                self.n_acc.zero_()
             for i in range(nb):
-                ctx.advance(self.walkers, self.w, self.key, self.step, self.delta, self.tau)
+                ctx.advance(self.walkers, self.w, self.key, self.step, self.delta, self.tau, self.n_acc)
                 if self.want_grad:
                     ctx.step_accumulate(self.walkers, self.tau, hist[i], self.acc["eps_s"], self.acc["eps_c"],
                                         self.acc["c_s"], self.acc["c_c"])
@@ -124,7 +233,34 @@ class Chain:
                 self.step += 1
             with torch.cuda.stream(ctx.stream):
                 self.values.append(hist.mean(dim=1).cpu().numpy())
+                acc = int(self.n_acc.item())
+            self.accepted += acc
+            self.proposed += nb * ctx.m
             done += nb
+            self._blocks += 1
+            if self.run_dir is not None:
+                self._record(nb, acc, time.perf_counter() - t0)
+                if self.checkpoint_every > 0 and self._blocks % self.checkpoint_every == 0:
+                    self.checkpoint()
+
+    def _record(self, nb: int, acc: int, seconds: float) -> None:
+        x = self.series()
+        rec = {"N": int(len(x)), "step": int(self.step), "key": list(self.key),
+               "I_N": [float(v) for v in x.mean(axis=0)],
+               "sigma_bar_N": [float(blocking_sigma(x[:, j])) for j in range(3)],
+               "acceptance": acc / float(nb * self.ctx.m), "steps_per_s": nb / seconds}
+        with open(os.path.join(self.run_dir, "records.jsonl"), "a") as fh:
+            fh.write(json.dumps(rec) + "\n")
+            fh.flush()
+            os.fsync(fh.fileno())
+
+    def checkpoint(self) -> str:
+        """Write a checkpoint into the run directory and keep the newest two."""
+        path = checkpoint_path(self.run_dir, self.step)
+        self.save(path)
+        for old in sorted(glob.glob(os.path.join(self.run_dir, "chain-*.npz")))[:-2]:
+            os.remove(old)
+        return path
 
     # -- results ----------------------------------------------------------------
     def series(self) -> np.ndarray:
@@ -145,9 +281,11 @@ class Chain:
     # -- checkpoint / resume ------------------------------------------------------
     def state_dict(self) -> dict:
         torch.cuda.current_stream().wait_stream(self.ctx.stream)
-        st = {"walkers": self.walkers.cpu().numpy(), "w": self.w.cpu().numpy(), "key": np.array(self.key),
+        st = {"format": np.int64(CHECKPOINT_FORMAT), "walkers": self.walkers.cpu().numpy(),
+              "w": self.w.cpu().numpy(), "key": np.array(self.key),
               "step": np.int64(self.step), "n_burn": np.int64(self.n_burn), "delta": np.float64(self.delta),
-              "n_tau": np.int64(self.n_tau), "values": self.series()}
+              "n_tau": np.int64(self.n_tau), "values": self.series(), "want_grad": np.bool_(self.want_grad),
+              "accepted": np.int64(self.accepted), "proposed": np.int64(self.proposed)}
         if self.want_grad:
             for k, v in self.acc.items():
                 st["acc_" + k] = v.cpu().numpy()
@@ -155,21 +293,43 @@ class Chain:
 
     def save(self, path: str):
         """Write the chain state (walkers, weights, counters, delta, the
-        per-step series and gradient accumulators) as an .npz file."""
-        np.savez(path, **self.state_dict())
+        per-step series and gradient accumulators) as an .npz file, atomically
+        (the file at `path` is the old one or the complete new one)."""
+        atomic_savez(path, **self.state_dict())
 
     @classmethod
-    def load(cls, ctx: Context, path: str, want_grad: bool = False) -> "Chain":
-        """Resume a saved chain on a context built from the same inputs."""
-        st = np.load(path, allow_pickle=False)
+    def load(cls, ctx: Context, path: str, want_grad: bool = None, run_dir: str = None,
+             checkpoint_every: int = 1) -> "Chain":
+        """Resume a saved chain on a context built from the same inputs.
+        Whether the chain accumulates gradients comes from the checkpoint;
+        a want_grad that contradicts it raises ValueError."""
+        st = read_checkpoint(path)
+        if st is None:
+            raise ValueError(f"{path} is not a complete chain checkpoint")
+        saved_grad = bool(st["want_grad"])
+        if want_grad is not None and bool(want_grad) != saved_grad:
+            raise ValueError(f"checkpoint has want_grad={saved_grad}, caller asked for {bool(want_grad)}")
         ch = cls(ctx, st["walkers"], key=tuple(int(k) for k in st["key"]), delta=float(st["delta"]),
-                 n_tau=int(st["n_tau"]), want_grad=want_grad)
+                 n_tau=int(st["n_tau"]), want_grad=saved_grad, run_dir=run_dir, checkpoint_every=checkpoint_every)
         with torch.cuda.stream(ctx.stream):
             ch.w.copy_(torch.as_tensor(st["w"], device=ch.w.device))
-            if want_grad:
+            if saved_grad:
                 for k in ch.acc:
                     ch.acc[k].copy_(torch.as_tensor(st["acc_" + k], device=ch.w.device))
         ch.step, ch.n_burn = int(st["step"]), int(st["n_burn"])
+        ch.accepted, ch.proposed = int(st["accepted"]), int(st["proposed"])
         vals = st["values"]
         ch.values = [vals] if len(vals) else []
+        return ch
+
+    @classmethod
+    def resume(cls, ctx: Context, run_dir: str, checkpoint_every: int = 1) -> "Chain":
+        """Continue the run in `run_dir` from its newest complete checkpoint;
+        records written after that checkpoint are dropped (the resumed chain
+        writes them again, identically)."""
+        path = latest_checkpoint(run_dir)
+        if path is None:
+            raise FileNotFoundError(f"no complete checkpoint in {run_dir}")
+        ch = cls.load(ctx, path, run_dir=run_dir, checkpoint_every=checkpoint_every)
+        truncate_records(run_dir, len(ch.series()))
         return ch

@@ -92,11 +92,14 @@ class Context:
 
     # --- entry points -------------------------------------------------------------------------
     def step(self, walkers: torch.Tensor, tau: torch.Tensor, e2_out: torch.Tensor,
-             grad_eps: torch.Tensor = None, grad_coeffs: torch.Tensor = None) -> torch.Tensor:
+             grad_eps: torch.Tensor = None, grad_coeffs: torch.Tensor = None,
+             value: torch.Tensor = None) -> torch.Tensor:
+        """One step; value (float64 [1], optional) receives the tau average of e2_out[:, 2]."""
         n_tau = int(tau.shape[0])
         check(self._lib.mcmp2_step(
             self._h, _dev(walkers, (self.m, 2, 3), name="walkers"), _dev(tau, (n_tau,), name="tau"), n_tau,
             _dev(e2_out, (n_tau, 3), name="e2_out"),
+            None if value is None else _dev(value, (1,), name="value"),
             None if grad_eps is None else _dev(grad_eps, (self.n_sp,), name="grad_eps"),
             None if grad_coeffs is None else _dev(grad_coeffs, (2, self.n_b, self.n_sp), torch.complex128,
                                                   name="grad_coeffs")))

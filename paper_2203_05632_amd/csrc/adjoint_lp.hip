@@ -209,11 +209,14 @@ hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
     const int n_row_tiles = (c->R + ABM - 1) / ABM;
     const int n_items = n_row_tiles * n_col_tiles;
     const int per = (n_items + 7) / 8;
+    const int ps = prof_begin(c, MCMP2_K_ADJ_GEMM);
     adj_lp_kernel<WN><<<8 * per, 256, 0, c->stream>>>(
         reinterpret_cast<const uint32_t *>(c->Hm), reinterpret_cast<const uint32_t *>(c->Hp), c->Vt,
         reinterpret_cast<const float2 *>(c->psi), tau, n_tau, c->R, c->no, c->nsp, n_occ_tiles, n_col_tiles, n_items,
         reinterpret_cast<double2 *>(c->psibar), c->eps_part);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return prof_end(c, ps, MCMP2_K_ADJ_GEMM);
 }
 
 }  // namespace

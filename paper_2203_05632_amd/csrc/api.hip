@@ -62,22 +62,14 @@ int check_hip(hipError_t e, const char *what) {
 
 namespace {
 // Launch through `fn`, bracketed by an event pair when kernel `kid` is being timed.
+// The stage's slot is taken before fn runs, so dispatch-level pairs recorded
+// inside fn (prof_begin / prof_end) take the slots after it.
 template <class F>
 int timed(mcmp2_ctx *c, int kid, const char *what, F fn) {
-    Profiler &p = c->prof;
-    const bool rec = (p.mask >> kid & 1u) && p.used < p.capacity;
-    if (rec) {
-        int rc = check_hip(hipEventRecord(p.ev[2 * p.used], c->stream), "hipEventRecord");
-        if (rc != MCMP2_OK) return rc;
-    }
+    const int slot = prof_begin(c, kid);
     int rc = check_hip(fn(), what);
     if (rc != MCMP2_OK) return rc;
-    if (rec) {
-        rc = check_hip(hipEventRecord(p.ev[2 * p.used + 1], c->stream), "hipEventRecord");
-        if (rc != MCMP2_OK) return rc;
-        p.kid[p.used++] = kid;
-    }
-    return MCMP2_OK;
+    return check_hip(prof_end(c, slot, kid), "hipEventRecord");
 }
 
 void profiler_release(Profiler &p) {
@@ -331,7 +323,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
 
 // One step (Eq. redundant) with the gradients, if any, going to geps / gcoef.
 static int run_step(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
-                    grad_out geps, grad_out gcoef) {
+                    double *value, grad_out geps, grad_out gcoef) {
     if (!c || !walkers || !tau || !e2_out) {
         set_error("null argument");
         return MCMP2_EINVAL;
@@ -362,6 +354,7 @@ static int run_step(mcmp2_ctx *c, const double *walkers, const double *tau, int3
         return rc;
     if ((rc = timed(c, MCMP2_K_REDUCE, "reduce", [&] { return launch_reduce(c, n_tau, e2_out); })) != MCMP2_OK)
         return rc;
+    if (value && (rc = check_hip(launch_step_value(c, e2_out, n_tau, value), "step_value")) != MCMP2_OK) return rc;
     if (!grad) return MCMP2_OK;
     if ((rc = timed(c, MCMP2_K_GRAD, "adjoint", [&] { return launch_adjoint(c, tau, n_tau, geps); })) != MCMP2_OK)
         return rc;
@@ -370,11 +363,11 @@ static int run_step(mcmp2_ctx *c, const double *walkers, const double *tau, int3
 }
 
 extern "C" int mcmp2_step(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
-                          double *grad_eps, double *grad_coeffs) {
+                          double *value, double *grad_eps, double *grad_coeffs) {
     grad_out geps, gcoef;
     geps.out = grad_eps;
     gcoef.out = grad_coeffs;
-    return run_step(c, walkers, tau, n_tau, e2_out, geps, gcoef);
+    return run_step(c, walkers, tau, n_tau, e2_out, value, geps, gcoef);
 }
 
 extern "C" int mcmp2_step_accumulate(mcmp2_ctx *c, const double *walkers, const double *tau, int32_t n_tau,
@@ -392,7 +385,7 @@ extern "C" int mcmp2_step_accumulate(mcmp2_ctx *c, const double *walkers, const 
     if (c && c->gstage) {  // small BF16 / FP16 problems: gradients staged, then added
         geps.out = c->gstage;
         gcoef.out = c->gstage + ((c->nsp + 1) & ~1);
-        int rc = run_step(c, walkers, tau, n_tau, e2_out, geps, gcoef);
+        int rc = run_step(c, walkers, tau, n_tau, e2_out, nullptr, geps, gcoef);
         if (rc != MCMP2_OK) return rc;
         if ((rc = timed(c, MCMP2_K_ACCUMULATE, "accumulate",
                         [&] { return launch_accumulate(c, geps.out, eps_sum, eps_comp, c->nsp); })) != MCMP2_OK)
@@ -404,7 +397,7 @@ extern "C" int mcmp2_step_accumulate(mcmp2_ctx *c, const double *walkers, const 
     geps.comp = eps_comp;
     gcoef.sum = coeffs_sum;
     gcoef.comp = coeffs_comp;
-    return run_step(c, walkers, tau, n_tau, e2_out, geps, gcoef);
+    return run_step(c, walkers, tau, n_tau, e2_out, nullptr, geps, gcoef);
 }
 
 extern "C" int mcmp2_set_interaction(mcmp2_ctx *c, int32_t interaction) {
@@ -553,6 +546,7 @@ extern "C" int mcmp2_profile_end(mcmp2_ctx *c, double *total_ms, int64_t *launch
     double ms[MCMP2_NKERNELS] = {0};
     int64_t n[MCMP2_NKERNELS] = {0};
     for (int i = 0; i < p.used && rc == MCMP2_OK; ++i) {
+        if (p.kid[i] < 0) continue;  // a pair whose stop event was not recorded
         float t = 0.f;
         rc = check_hip(hipEventElapsedTime(&t, p.ev[2 * i], p.ev[2 * i + 1]), "hipEventElapsedTime");
         ms[p.kid[i]] += t;

@@ -350,6 +350,7 @@ hipError_t launch_grad_gemm(const mcmp2_ctx *c, const double *tau, int n_tau, in
     for (int t0 = 0; t0 < n_tau; t0 += 2) {
         const int nt = std::min(2, n_tau - t0);
         const bool acc = t0 > 0;
+        const int ps = prof_begin(c, MCMP2_K_ADJ_GEMM);
         if (nt == 2)
             grad_gemm_kernel<2, P><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
                                                                 n_occ_tiles, acc, psibar, c->eps_part);
@@ -358,6 +359,7 @@ hipError_t launch_grad_gemm(const mcmp2_ctx *c, const double *tau, int n_tau, in
                                                                 n_occ_tiles, acc, psibar, c->eps_part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if ((e = prof_end(c, ps, MCMP2_K_ADJ_GEMM)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

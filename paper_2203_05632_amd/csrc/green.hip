@@ -351,6 +351,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ 
     reduce_tau(partial, n_slots, blockIdx.x, inv_pairs, e2_out, sh);
 }
 
+// The step value V = (1/n_tau) sum_t e2_out[t][2] (the tau average of
+// Eq. redundant's pair averages), summed in tau order with compensation.
+__global__ __launch_bounds__(64) void step_value_kernel(const double *__restrict__ e2_out, int n_tau,
+                                                        double *__restrict__ value) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (int t = 0; t < n_tau; ++t) neumaier_add(s, c, e2_out[3 * t + 2]);
+    value[0] = (s + c) / (double)n_tau;
+}
+
 }  // namespace
 
 // Tile pairs (P <= Q) of T block tiles are grouped into super-blocks of bands
@@ -428,7 +438,7 @@ namespace {
 // One launch of NTV tau samples per block: the gradient variant, the Gaunt /
 // Breit variant (one tau per block only) or the plain estimator.
 template <typename T, int NTV>
-void launch_green_nt(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, double cgrad) {
+void launch_green_dispatch(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, double cgrad) {
     double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
     if (grad) {
         green_contract_kernel<T, NTV, true, false><<<grid, 256, 0, c->stream>>>(
@@ -448,6 +458,13 @@ void launch_green_nt(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, doubl
     green_contract_kernel<T, NTV, false, false><<<grid, 256, 0, c->stream>>>(
         c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m, c->partial,
         nullptr, nullptr, 0.0, c->rhat, 0.0);
+}
+
+template <typename T, int NTV>
+void launch_green_nt(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, double cgrad) {
+    const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
+    launch_green_dispatch<T, NTV>(c, grid, grad, breit, cgrad);
+    (void)prof_end(c, ps, MCMP2_K_GREEN_GEMM);
 }
 
 template <typename T>
@@ -482,5 +499,10 @@ hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out) {
     const double inv_pairs = 1.0 / (0.5 * (double)c->m * (double)(c->m - 1));
     const int n_slots = green_big_selected(c, n_tau) ? 8 * c->n_tp16 : c->n_slots;
     reduce_kernel<<<n_tau, 256, 0, c->stream>>>(c->partial, n_slots, inv_pairs, e2_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_value(const mcmp2_ctx *c, const double *e2_out, int n_tau, double *value) {
+    step_value_kernel<<<1, 64, 0, c->stream>>>(e2_out, n_tau, value);
     return hipGetLastError();
 }

@@ -408,6 +408,7 @@ hipError_t launch_big_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     const uint32_t *U = reinterpret_cast<const uint32_t *>(c->U);
     uint32_t *Hm = reinterpret_cast<uint32_t *>(c->Hm), *Hp = reinterpret_cast<uint32_t *>(c->Hp);
+    const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
     if (grad)
         green_big_kernel<T, true><<<8 * per, 512, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau, c->hinv,
                                                                   c->tiles16, c->n_tp16, n_items, c->R, c->m,
@@ -416,7 +417,9 @@ hipError_t launch_big_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
         green_big_kernel<T, false><<<8 * per, 512, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau, c->hinv,
                                                                    c->tiles16, c->n_tp16, n_items, c->R, c->m,
                                                                    c->partial, nullptr, nullptr, 0.0);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return prof_end(c, ps, MCMP2_K_GREEN_GEMM);
 }
 
 template <typename T>
@@ -446,6 +449,7 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
         green_lp_kernel<T, NTV, false, uint32_t><<<nblocks, 256, 0, c->stream>>>(                                \
             U, c->Ko, c->Ktot, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->m, t0, c->partial,      \
             nullptr, nullptr, 0.0)
+        const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
         switch (nt) {
             case 1: LP_LAUNCH(1); break;
             case 2: LP_LAUNCH(2); break;
@@ -455,6 +459,7 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
 #undef LP_LAUNCH
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if ((e = prof_end(c, ps, MCMP2_K_GREEN_GEMM)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

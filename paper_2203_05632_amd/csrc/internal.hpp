@@ -128,6 +128,28 @@ __device__ inline double g_value(double x, double y, double z, const double *nuc
     return out;
 }
 
+// Event pair around a single kernel dispatch when kernel id `kid` is being
+// timed (mcmp2_profile_begin): prof_begin() records the start event and
+// returns the slot (-1 when not recording), prof_end() the stop event.  The
+// launchers bracket their main GEMM dispatch with it (MCMP2_K_GREEN_GEMM,
+// MCMP2_K_ADJ_GEMM), inside the stage-level pairs of the C ABI.
+inline int prof_begin(const mcmp2_ctx *c, int kid) {
+    Profiler &p = const_cast<Profiler &>(c->prof);
+    if (!((p.mask >> kid) & 1u) || p.used >= p.capacity) return -1;
+    const int slot = p.used;
+    if (hipEventRecord(p.ev[2 * slot], c->stream) != hipSuccess) return -1;
+    p.kid[slot] = -1;  // filled in by prof_end
+    ++p.used;
+    return slot;
+}
+inline hipError_t prof_end(const mcmp2_ctx *c, int slot, int kid) {
+    if (slot < 0) return hipSuccess;
+    Profiler &p = const_cast<Profiler &>(c->prof);
+    hipError_t e = hipEventRecord(p.ev[2 * slot + 1], c->stream);
+    if (e == hipSuccess) p.kid[slot] = kid;
+    return e;
+}
+
 // Host: wave-slot work list of the Green's-function kernel (see green.hip).
 void build_green_work(int T, double tile_bytes, std::vector<int> &work);
 
@@ -168,3 +190,5 @@ hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, grad_out grad_coeffs);
 bool coef_grad_lp_fused(const mcmp2_ctx *c);
 int adjoint_lp_row_tiles(const mcmp2_ctx *c);
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out);
+// value[0] = (1/n_tau) sum_t e2_out[t][2]
+hipError_t launch_step_value(const mcmp2_ctx *c, const double *e2_out, int n_tau, double *value);

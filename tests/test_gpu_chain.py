@@ -81,3 +81,53 @@ def test_chains_on_concurrent_streams_match_sequential_runs():
     m = merge([ch.result() for ch in par])
     assert m.steps == 450
     assert np.allclose(m.mean, np.mean([ch.result().mean for ch in par], axis=0))
+
+
+@pytest.mark.parametrize("grad", [False, True])
+def test_run_directory_resume_after_a_stop(tmp_path, grad):
+    """A chain writing records and checkpoints into a run directory is
+    stopped after its second block (a clean stop) and its context released;
+    a fresh context resumes from the directory -- past a torn temporary file
+    and a damaged newer checkpoint -- and ends bit for bit where an
+    uninterrupted run ends: per-step series, walkers, gradient sums and the
+    block records (except their wall-clock rates).  Whether the chain
+    accumulates gradients comes from the checkpoint."""
+    from paper_2203_05632_amd import Chain, Context
+    from paper_2203_05632_amd.chain import checkpoint_path, read_records
+    inp = make_inputs("C0", n_tau=2)
+    da, db = str(tmp_path / "a"), str(tmp_path / "b")
+
+    def fresh(run_dir):
+        ctx = Context.from_inputs(inp, want_grad=grad)
+        return Chain(ctx, initial_walkers(inp, chain=1), key=(3, 1), delta=0.4, want_grad=grad, run_dir=run_dir)
+
+    a = fresh(da)
+    a.burn_in(60)
+    a.run(400, block=100)
+    b = fresh(db)
+    b.burn_in(60)
+    b.run(200, block=100)
+    stop_step = b.step
+    b.ctx.close()
+    del b
+    good = open(checkpoint_path(db, stop_step), "rb").read()
+    with open(checkpoint_path(db, stop_step + 100), "wb") as fh:      # damaged newer checkpoint
+        fh.write(good[: len(good) // 3])
+    with open(checkpoint_path(db, stop_step + 200) + ".123.tmp", "wb") as fh:
+        fh.write(good[:64])
+    c = Chain.resume(Context.from_inputs(inp, want_grad=grad), db)
+    assert c.want_grad == grad and c.step == stop_step
+    c.run(200, block=100)
+    assert np.array_equal(a.series(), c.series())
+    assert np.array_equal(a.walkers.cpu().numpy(), c.walkers.cpu().numpy())
+    ra, rc = a.result(), c.result()
+    assert np.array_equal(ra.mean, rc.mean) and np.array_equal(ra.sigma, rc.sigma)
+    if grad:
+        assert np.array_equal(ra.grad_eps, rc.grad_eps) and np.array_equal(ra.grad_coeffs, rc.grad_coeffs)
+    recs_a, recs_c = read_records(da), read_records(db)
+    assert [r["N"] for r in recs_a] == [100, 200, 300, 400]
+    for x, y in zip(recs_a, recs_c):
+        x.pop("steps_per_s"), y.pop("steps_per_s")
+    assert recs_a == recs_c
+    assert recs_a[-1]["I_N"] == [float(v) for v in ra.mean]
+    assert 0.0 < recs_a[-1]["acceptance"] < 1.0

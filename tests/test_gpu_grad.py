@@ -132,6 +132,34 @@ def test_autograd_function_and_finite_differences():
                 assert abs(2.0 * fd.item() - an.item()) <= 1e-6 * gC.abs().max().item()
 
 
+def test_autograd_function_on_a_side_stream_context():
+    """A context on its own stream gives the value and gradients of a
+    default-stream context bit for bit, with inputs produced on the current
+    stream just before the call (the function orders the two streams)."""
+    from paper_2203_05632_amd import mcmp2_value
+    inp = make_inputs("C1")
+    wk = dev(initial_walkers(inp))
+    taus = dev([0.35, 1.2])
+    side = torch.cuda.Stream()
+    out = []
+    for ctx in (_ctx(inp), _ctx(inp, stream=side)):
+        # inputs written by a kernel on the current stream right before the call
+        C = torch.tensor(inp.coeffs, dtype=torch.complex128, device="cuda") * 1.0
+        e = torch.tensor(inp.eps, dtype=torch.float64, device="cuda") * 1.0
+        C.requires_grad_(True)
+        e.requires_grad_(True)
+        V = mcmp2_value(C, e, wk, taus, ctx)
+        V.backward()
+        out.append((V.detach().clone(), C.grad.clone(), e.grad.clone()))
+    torch.cuda.synchronize()
+    e2 = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    _ctx(inp).step(wk, taus, e2)
+    torch.cuda.synchronize()
+    assert abs(out[0][0].item() - e2[:, 2].mean().item()) <= 1e-15 * abs(e2[:, 2].mean().item())
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+
+
 def test_gradient_needs_want_grad():
     from paper_2203_05632_amd import Context, MCMP2Error
     inp = make_inputs("C0")
