@@ -277,6 +277,33 @@ enum {
 int mcmp2_profile_begin(mcmp2_ctx *ctx, uint32_t mask, int32_t max_launches);
 int mcmp2_profile_end(mcmp2_ctx *ctx, double *total_ms, int64_t *launches);
 
+/*
+ * mcmp2_step_noalloc -- for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): mcmp2_step of an
+ * FP64 context with the Coulomb interaction and no gradients, without a
+ * context.  It makes no device allocation: the step's buffers (packed basis
+ * records, basis values, spinor values, tau scalings, work lists, per-wave
+ * partial sums) live in a fixed 32 MiB device array of the library, one per
+ * device, held until the process ends.
+ *   basis, eps, n_occ, n_vir, m_pairs : as for mcmp2_init (host memory, read
+ *                 during the call).
+ *   coeffs      : DEVICE complex [2][n_L+n_S][n_occ+n_vir] (the layout of
+ *                 mcmp2_init's coeffs), read in place.
+ *   walkers, tau, n_tau, e2_out, value : as for mcmp2_step (device); n_tau >= 1.
+ *   hip_stream  : hipStream_t to enqueue on (NULL = default stream).
+ * Results equal mcmp2_step's on an FP64 context built from the same inputs.
+ * The call synchronises hip_stream before returning.  Every call on a device
+ * shares that device's array, and the array keeps the last call's contents
+ * (the call clears what must start at zero): calls that overlap on one
+ * device, from several threads or streams, race.
+ * Errors: EINVAL (as mcmp2_init and mcmp2_step; a problem whose buffers
+ * exceed the 32 MiB array, e.g. m = 128 walker pairs with 660 primitives and
+ * 340 spinors needs about 7 MB), EDEVICE.
+ */
+int mcmp2_step_noalloc(const mcmp2_basis *basis, const double *coeffs, const double *eps, int32_t n_occ,
+                       int32_t n_vir, int32_t m_pairs, const double *walkers, const double *tau, int32_t n_tau,
+                       double *e2_out, double *value, void *hip_stream);
+
 /* Release the context and its device memory (synchronises its stream). NULL is ignored. */
 void mcmp2_destroy(mcmp2_ctx *ctx);
 

@@ -8,5 +8,5 @@ and never computes any step of the method itself.
 """
 from .autograd import MCMP2Step, mcmp2_value  # noqa: F401
 from .chain import Chain, ChainResult, blocking_sigma, merge  # noqa: F401
-from .context import Context  # noqa: F401
+from .context import Context, step_noalloc  # noqa: F401
 from ._lib import EXPORTS, MCMP2Error, PRECISIONS, load  # noqa: F401

@@ -17,8 +17,8 @@ INTERACTIONS = {"coulomb": 0, "gaunt": 1, "breit": 2}
 
 # Every symbol declared in include/mcmp2.h.
 EXPORTS = ["mcmp2_init", "mcmp2_step", "mcmp2_step_accumulate", "mcmp2_set_coefficients", "mcmp2_set_interaction", "mcmp2_pair_weights", "mcmp2_metropolis", "mcmp2_sample_tau",
-           "mcmp2_advance", "mcmp2_accumulate", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_destroy",
-           "mcmp2_last_error"]
+           "mcmp2_advance", "mcmp2_accumulate", "mcmp2_constants", "mcmp2_profile_begin", "mcmp2_profile_end", "mcmp2_step_noalloc",
+           "mcmp2_destroy", "mcmp2_last_error"]
 KERNELS = ["walker_weights", "step_prep", "spinor_gemm", "green_contract", "reduce", "metropolis", "sample_tau",
            "advance", "grad", "accumulate", "coef_grad", "green_gemm", "adj_gemm"]
 
@@ -81,6 +81,8 @@ def load() -> ctypes.CDLL:
     lib.mcmp2_profile_begin.restype = ctypes.c_int
     lib.mcmp2_profile_end.argtypes = [vp, vp, vp]
     lib.mcmp2_profile_end.restype = ctypes.c_int
+    lib.mcmp2_step_noalloc.argtypes = [ctypes.POINTER(Basis), vp, vp, i32, i32, i32, vp, vp, i32, vp, vp, vp]
+    lib.mcmp2_step_noalloc.restype = ctypes.c_int
     lib.mcmp2_destroy.argtypes = [vp]
     lib.mcmp2_destroy.restype = None
     lib.mcmp2_last_error.argtypes = []

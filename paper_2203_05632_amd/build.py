@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcmp2.so")
-SOURCES = ["api.hip", "sampling.hip", "spinor.hip", "green.hip", "green_lp.hip", "grad.hip", "adjoint_lp.hip", "spinor_lp.hip"]
+SOURCES = ["api.hip", "sampling.hip", "spinor.hip", "green.hip", "green_lp.hip", "grad.hip", "adjoint_lp.hip", "spinor_lp.hip", "noalloc.hip"]
 HEADERS = ["internal.hpp", "contract.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -30,6 +30,50 @@ def _dev(t: torch.Tensor, shape=None, dtype=torch.float64, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _basis(nuc_xyz, wfn, n_L: int, n_S: int, prim_xyz, prim_exp, prim_lxyz, prim_norm):
+    """mcmp2_basis over contiguous host copies (returned with the copies, which must outlive the call)."""
+    n_b = int(n_L) + int(n_S)
+    keep = dict(nuc=_host(nuc_xyz, np.float64), wfn=_host(wfn, np.float64), pxyz=_host(prim_xyz, np.float64),
+                pexp=_host(prim_exp, np.float64), plxyz=_host(prim_lxyz, np.int32),
+                pnorm=_host(prim_norm, np.float64))
+    n_nuc = keep["nuc"].shape[0]
+    if keep["nuc"].shape != (n_nuc, 3) or keep["wfn"].shape != (n_nuc, 4):
+        raise ValueError("nuc_xyz must be [n_nuc, 3] and wfn [n_nuc, 4]")
+    for k, shp in (("pxyz", (n_b, 3)), ("plxyz", (n_b, 3)), ("pexp", (n_b,)), ("pnorm", (n_b,))):
+        if keep[k].shape != shp:
+            raise ValueError(f"basis array {k} has shape {keep[k].shape}, expected {shp}")
+    basis = Basis(n_nuc, keep["nuc"].ctypes.data, keep["wfn"].ctypes.data, int(n_L), int(n_S),
+                  keep["pxyz"].ctypes.data, keep["pexp"].ctypes.data, keep["plxyz"].ctypes.data,
+                  keep["pnorm"].ctypes.data)
+    return basis, keep
+
+
+def step_noalloc(inp, coeffs: torch.Tensor, walkers: torch.Tensor, tau: torch.Tensor, e2_out: torch.Tensor,
+                 value: torch.Tensor = None, stream: torch.cuda.Stream = None) -> torch.Tensor:
+    """mcmp2_step_noalloc: the FP64 estimator without a context or any device
+    allocation.  `inp` carries the mcmp2_basis fields, eps, n_occ, n_vir and m;
+    coeffs is a complex128 device tensor [2, n_b, n_sp]; walkers, tau, e2_out
+    and value as for Context.step.  Synchronises the stream before returning."""
+    lib = load()
+    basis, keep = _basis(inp.nuc_xyz, inp.wfn, inp.n_L, inp.n_S, inp.prim_xyz, inp.prim_exp, inp.prim_lxyz,
+                         inp.prim_norm)
+    n_sp = int(inp.n_occ) + int(inp.n_vir)
+    eps = _host(inp.eps, np.float64)
+    if eps.shape != (n_sp,):
+        raise ValueError("eps must have n_occ + n_vir entries")
+    n_tau = int(tau.shape[0])
+    m = int(walkers.shape[0])
+    st = torch.cuda.current_stream() if stream is None else stream
+    check(lib.mcmp2_step_noalloc(
+        ctypes.byref(basis), _dev(coeffs, (2, int(inp.n_L) + int(inp.n_S), n_sp), torch.complex128, name="coeffs"),
+        ctypes.c_void_p(eps.ctypes.data), int(inp.n_occ), int(inp.n_vir), m,
+        _dev(walkers, (m, 2, 3), name="walkers"), _dev(tau, (n_tau,), name="tau"), n_tau,
+        _dev(e2_out, (n_tau, 3), name="e2_out"), None if value is None else _dev(value, (1,), name="value"),
+        ctypes.c_void_p(st.cuda_stream)))
+    del keep
+    return e2_out
+
+
 class Context:
     """Owns one mcmp2_ctx (device copies of basis, coefficients, energies and
     every per-step work buffer)."""
@@ -44,26 +88,13 @@ class Context:
         self.n_sp = self.n_occ + self.n_vir
         self.n_b = int(n_L) + int(n_S)
         self.stream = torch.cuda.current_stream() if stream is None else stream
-        keep = dict(
-            nuc=_host(nuc_xyz, np.float64), wfn=_host(wfn, np.float64), pxyz=_host(prim_xyz, np.float64),
-            pexp=_host(prim_exp, np.float64), plxyz=_host(prim_lxyz, np.int32),
-            pnorm=_host(prim_norm, np.float64), eps=_host(eps, np.float64),
-        )
+        basis, keep = _basis(nuc_xyz, wfn, n_L, n_S, prim_xyz, prim_exp, prim_lxyz, prim_norm)
+        keep["eps"] = _host(eps, np.float64)
         C = np.ascontiguousarray(np.asarray(coeffs, dtype=np.complex128))
         if C.shape != (2, self.n_b, self.n_sp):
             raise ValueError(f"coeffs has shape {C.shape}, expected {(2, self.n_b, self.n_sp)}")
         if keep["eps"].shape != (self.n_sp,):
             raise ValueError("eps must have n_occ + n_vir entries")
-        n_nuc = keep["nuc"].shape[0]
-        if keep["nuc"].shape != (n_nuc, 3) or keep["wfn"].shape != (n_nuc, 4):
-            raise ValueError("nuc_xyz must be [n_nuc, 3] and wfn [n_nuc, 4]")
-        for k, shp in (("pxyz", (self.n_b, 3)), ("plxyz", (self.n_b, 3)), ("pexp", (self.n_b,)),
-                       ("pnorm", (self.n_b,))):
-            if keep[k].shape != shp:
-                raise ValueError(f"basis array {k} has shape {keep[k].shape}, expected {shp}")
-        basis = Basis(n_nuc, keep["nuc"].ctypes.data, keep["wfn"].ctypes.data, int(n_L), int(n_S),
-                      keep["pxyz"].ctypes.data, keep["pexp"].ctypes.data, keep["plxyz"].ctypes.data,
-                      keep["pnorm"].ctypes.data)
         check(lib.mcmp2_init(ctypes.byref(basis), ctypes.c_void_p(C.ctypes.data),
                              ctypes.c_void_p(keep["eps"].ctypes.data), self.n_occ, self.n_vir, self.m,
                              self.n_tau_max, PRECISIONS[precision], int(bool(want_grad)),

@@ -94,15 +94,8 @@ void profiler_release(Profiler &p) {
 
 extern "C" const char *mcmp2_last_error(void) { return g_err; }
 
-extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps, int32_t n_occ,
-                          int32_t n_vir, int32_t m_pairs, int32_t n_tau_max, int32_t precision, int32_t want_grad,
-                          void *hip_stream, mcmp2_ctx **out) {
-    g_err[0] = '\0';
-    if (!out) {
-        set_error("out is NULL");
-        return MCMP2_EINVAL;
-    }
-    *out = nullptr;
+int check_setup(const mcmp2_basis *basis, const double *coeffs, const double *eps, int n_occ, int n_vir,
+                int m_pairs, int n_tau_max, int precision, double *lambda_out) {
     if (!basis || !coeffs || !eps || !basis->nuc_xyz || !basis->wfn || !basis->prim_xyz || !basis->prim_exp ||
         !basis->prim_lxyz || !basis->prim_norm) {
         set_error("null input pointer");
@@ -146,15 +139,14 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
         set_error("lambda = 2 (eps_LUMO - eps_HOMO) = %g must be positive", lambda);
         return MCMP2_EINVAL;
     }
+    *lambda_out = lambda;
+    return MCMP2_OK;
+}
 
-    mcmp2_ctx *c = new (std::nothrow) mcmp2_ctx();
-    if (!c) {
-        set_error("host allocation failed");
-        return MCMP2_ENOMEM;
-    }
+int setup_ctx(mcmp2_ctx *c, const mcmp2_basis *basis, int n_occ, int n_vir, int m_pairs, int n_tau_max,
+              int precision, int want_grad, double lambda, void *hip_stream, std::vector<double> &gpar) {
     if (hipGetDevice(&c->device) != hipSuccess) {
         set_error("no HIP device");
-        delete c;
         return MCMP2_EDEVICE;
     }
     if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
@@ -164,10 +156,10 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     c->n_nuc = basis->n_nuc;
     c->nL = basis->n_L;
     c->nS = basis->n_S;
-    c->nb = nb;
+    c->nb = basis->n_L + basis->n_S;
     c->no = n_occ;
     c->nv = n_vir;
-    c->nsp = nsp;
+    c->nsp = n_occ + n_vir;
     c->m = m_pairs;
     c->m_pad = (m_pairs + kWalkerPad - 1) / kWalkerPad * kWalkerPad;
     c->E = 2 * c->m_pad;
@@ -183,10 +175,9 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     const int kq = 64;
     c->Ko = (2 * n_occ + kq - 1) / kq * kq;
     c->Ktot = c->Ko + (2 * n_vir + kq - 1) / kq * kq;
-    const size_t op_bytes = 2;
 
     // N_g = sum over all pairs of weight-function Gaussians (Sec. III).
-    std::vector<double> gpar(4 * (size_t)c->n_nuc);
+    gpar.assign(4 * (size_t)c->n_nuc, 0.0);
     double Ng = 0.0;
     for (int I = 0; I < c->n_nuc; ++I) {
         const double *w = basis->wfn + 4 * I;
@@ -206,14 +197,70 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
                           coulomb_ss(gpar[4 * I + 2 * ka + 1], gpar[4 * J + 2 * kb + 1], R2);
                 }
     c->Ng = Ng;
+    return MCMP2_OK;
+}
 
-    std::vector<int> tiles;
-    tiles.reserve(2 * (size_t)c->n_tp);
-    for (int P = 0; P < c->T; ++P)
-        for (int Q = P; Q < c->T; ++Q) {
+void triangle_tiles(int T, std::vector<int> &tiles) {
+    tiles.clear();
+    tiles.reserve((size_t)T * (T + 1));
+    for (int P = 0; P < T; ++P)
+        for (int Q = P; Q < T; ++Q) {
             tiles.push_back(P);
             tiles.push_back(Q);
         }
+}
+
+double green_tile_bytes(const mcmp2_ctx *c) {
+    // bytes of one block tile's operand rows: 8 kTileWalkers rows of all spinors
+    const double row_bytes = c->precision == MCMP2_FP64 ? 16.0 * c->nsp
+                             : c->precision == MCMP2_FP32 ? 8.0 * c->nsp
+                                                          : 2.0 * c->Ktot;
+    return 8.0 * kTileWalkers * row_bytes;
+}
+
+void pack_basis(const mcmp2_basis *basis, std::vector<double> &geo, std::vector<double> &nl) {
+    const int nb = basis->n_L + basis->n_S;
+    geo.assign(4 * (size_t)nb, 0.0);
+    nl.assign(2 * (size_t)nb, 0.0);
+    for (int i = 0; i < nb; ++i) {
+        for (int d = 0; d < 3; ++d) geo[4 * i + d] = basis->prim_xyz[3 * i + d];
+        geo[4 * i + 3] = basis->prim_exp[i];
+        nl[2 * i] = basis->prim_norm[i];
+        const int64_t packed = (int64_t)basis->prim_lxyz[3 * i] | ((int64_t)basis->prim_lxyz[3 * i + 1] << 8) |
+                               ((int64_t)basis->prim_lxyz[3 * i + 2] << 16);
+        std::memcpy(&nl[2 * i + 1], &packed, sizeof(double));
+    }
+}
+
+extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps, int32_t n_occ,
+                          int32_t n_vir, int32_t m_pairs, int32_t n_tau_max, int32_t precision, int32_t want_grad,
+                          void *hip_stream, mcmp2_ctx **out) {
+    g_err[0] = '\0';
+    if (!out) {
+        set_error("out is NULL");
+        return MCMP2_EINVAL;
+    }
+    *out = nullptr;
+    double lambda = 0.0;
+    int rc0 = check_setup(basis, coeffs, eps, n_occ, n_vir, m_pairs, n_tau_max, precision, &lambda);
+    if (rc0 != MCMP2_OK) return rc0;
+    const int nb = basis->n_L + basis->n_S;
+    const int nsp = n_occ + n_vir;
+
+    mcmp2_ctx *c = new (std::nothrow) mcmp2_ctx();
+    if (!c) {
+        set_error("host allocation failed");
+        return MCMP2_ENOMEM;
+    }
+    std::vector<double> gpar;
+    rc0 = setup_ctx(c, basis, n_occ, n_vir, m_pairs, n_tau_max, precision, want_grad, lambda, hip_stream, gpar);
+    if (rc0 != MCMP2_OK) {
+        delete c;
+        return rc0;
+    }
+    const size_t op_bytes = 2;
+    std::vector<int> tiles;
+    triangle_tiles(c->T, tiles);
 
     TRY(dalloc(&c->nuc, 3 * (size_t)c->n_nuc));
     TRY(dalloc(&c->gpar, 4 * (size_t)c->n_nuc));
@@ -253,11 +300,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(dalloc(&c->scale, (size_t)n_tau_max * nsp));
     TRY(dalloc(&c->wtau, (size_t)n_tau_max));
     std::vector<int> work;
-    // bytes of one block tile's operand rows: 8 kTileWalkers rows of all spinors
-    const double row_bytes = precision == MCMP2_FP64 ? 16.0 * nsp
-                             : precision == MCMP2_FP32 ? 8.0 * nsp
-                                                       : (double)op_bytes * c->Ktot;
-    build_green_work(c->T, 8.0 * kTileWalkers * row_bytes, work);
+    build_green_work(c->T, green_tile_bytes(c), work);
     c->n_slots = 4 * (int)work.size();
     TRY(dalloc(&c->tiles, 2 * (size_t)c->n_tp));
     TRY(dalloc(&c->work, work.size()));
@@ -294,15 +337,8 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
     TRY(up(c->nuc, basis->nuc_xyz, 3 * sizeof(double) * c->n_nuc));
     TRY(up(c->gpar, gpar.data(), gpar.size() * sizeof(double)));
     // packed primitive records: (A, zeta) and (N, powers as int64 bits)
-    std::vector<double> geo(4 * (size_t)nb), nl(2 * (size_t)nb);
-    for (int i = 0; i < nb; ++i) {
-        for (int d = 0; d < 3; ++d) geo[4 * i + d] = basis->prim_xyz[3 * i + d];
-        geo[4 * i + 3] = basis->prim_exp[i];
-        nl[2 * i] = basis->prim_norm[i];
-        const int64_t packed = (int64_t)basis->prim_lxyz[3 * i] | ((int64_t)basis->prim_lxyz[3 * i + 1] << 8) |
-                               ((int64_t)basis->prim_lxyz[3 * i + 2] << 16);
-        std::memcpy(&nl[2 * i + 1], &packed, sizeof(double));
-    }
+    std::vector<double> geo, nl;
+    pack_basis(basis, geo, nl);
     TRY(up(c->pgeo, geo.data(), geo.size() * sizeof(double)));
     TRY(up(c->pnl, nl.data(), nl.size() * sizeof(double)));
     TRY(up(c->coef, coeffs, 2 * 2 * sizeof(double) * (size_t)nb * nsp));

@@ -153,6 +153,22 @@ inline hipError_t prof_end(const mcmp2_ctx *c, int slot, int kid) {
 // Host: wave-slot work list of the Green's-function kernel (see green.hip).
 void build_green_work(int T, double tile_bytes, std::vector<int> &work);
 
+// Host set-up shared by mcmp2_init and mcmp2_step_noalloc (api.hip).
+// check_setup validates the set-up arguments (EINVAL with a message) and
+// returns lambda = 2 (eps_LUMO - eps_HOMO); setup_ctx fills the sizes,
+// padding and frozen constants of a context (no device memory) and the
+// weight-function records gpar; pack_basis packs the primitive records
+// (A, zeta) and (N, Cartesian powers as int64 bits); triangle_tiles lists the
+// walker-tile pairs P <= Q; green_tile_bytes is the operand bytes of one
+// Green's-kernel block tile (the work-list builder's L2 model).
+int check_setup(const mcmp2_basis *basis, const double *coeffs, const double *eps, int n_occ, int n_vir,
+                int m_pairs, int n_tau_max, int precision, double *lambda_out);
+int setup_ctx(mcmp2_ctx *c, const mcmp2_basis *basis, int n_occ, int n_vir, int m_pairs, int n_tau_max,
+              int precision, int want_grad, double lambda, void *hip_stream, std::vector<double> &gpar);
+void pack_basis(const mcmp2_basis *basis, std::vector<double> &geo, std::vector<double> &nl);
+void triangle_tiles(int T, std::vector<int> &tiles);
+double green_tile_bytes(const mcmp2_ctx *c);
+
 // error reporting (thread-local message)
 void set_error(const char *fmt, ...);
 int check_hip(hipError_t e, const char *what);
