@@ -27,7 +27,6 @@ from __future__ import annotations
 
 import glob
 import json
-import math
 import os
 import time
 from dataclasses import dataclass
@@ -39,15 +38,19 @@ import torch
 from .context import Context
 
 
-def blocking_sigma(x: np.ndarray, n_b: int = 100) -> float:
+def blocking_sigma(x: np.ndarray, n_b: int = 100):
     """Standard error of the mean of a correlated series (Sec. III): blocks of
     n_b consecutive values, population variance of the block means, divided
-    by the number of complete blocks; an incomplete last block is dropped."""
-    n_blocks = len(x) // n_b
+    by the number of complete blocks; an incomplete last block is dropped.
+    A 1-d series gives a float; an [N, ...] array gives one standard error per
+    trailing index (steps along axis 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    n_blocks = x.shape[0] // n_b
     if n_blocks < 2:
-        return float("nan")
-    means = np.asarray(x[: n_blocks * n_b], dtype=np.float64).reshape(n_blocks, n_b).mean(axis=1)
-    return float(math.sqrt(means.var() / n_blocks))
+        return float("nan") if x.ndim == 1 else np.full(x.shape[1:], np.nan)
+    means = x[: n_blocks * n_b].reshape((n_blocks, n_b) + x.shape[1:]).mean(axis=1)
+    sig = np.sqrt(means.var(axis=0) / n_blocks)
+    return float(sig) if x.ndim == 1 else sig
 
 
 @dataclass

@@ -246,7 +246,7 @@ def _loewdin(C: np.ndarray, S_blocks: Tuple[np.ndarray, np.ndarray], n_L: int) -
 
 def make_inputs(name: str = "C0", seed: int = 0, kappa_s: float = 0.1, mode: str = "dirac",
                 n_occ: int = None, n_vir: int = None, m: int = None, n_tau: int = None,
-                exp_range: Tuple[float, float] = None) -> Inputs:
+                exp_range: Tuple[float, float] = None, shell_reps: int = None) -> Inputs:
     """Build the synthetic workload `name` (C0..C4).
 
     mode = "dirac": general complex four-component Kramers pairs (S block
@@ -259,6 +259,11 @@ def make_inputs(name: str = "C0", seed: int = 0, kappa_s: float = 0.1, mode: str
     for k, v in (("n_occ", n_occ), ("n_vir", n_vir), ("m", m), ("n_tau", n_tau), ("exp_range", exp_range)):
         if v is not None:
             cfg[k] = v
+    if shell_reps is not None:  # a "cycle" plan with another number of repetitions (basis-size ladders)
+        kind, ls, _ = cfg["shell_plan"]
+        if kind != "cycle":
+            raise ValueError("shell_reps applies to workloads with a cycle shell plan")
+        cfg["shell_plan"] = (kind, ls, int(shell_reps))
     if cfg["n_occ"] % 2 or cfg["n_vir"] % 2:
         raise ValueError("Kramers pairs need even n_occ and n_vir")
     nuc, n_L, n_S, xyz, alpha, lxyz, shell = _build_basis(cfg, seed)

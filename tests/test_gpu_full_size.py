@@ -21,7 +21,10 @@ from synth import initial_walkers, make_inputs
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 TAUS = [0.12, 0.5, 1.3, 3.1]
-BOUND = {"fp64": 1e-10, "fp32": 1e-6, "bf16": 8 * 2.0 ** -8, "fp16": 8 * 2.0 ** -11}
+# FP64: the parity bar.  FP32 / BF16 / FP16: the regression guards of the
+# reduced-precision step tests (three times the largest deviation measured
+# there); measured here: FP32 6e-7, BF16 7e-4, FP16 9e-5 of the pair scale.
+BOUND = {"fp64": 1e-10, "fp32": 1e-6, "bf16": 1e-2, "fp16": 5e-4}
 
 
 @pytest.fixture(scope="module")

@@ -3,18 +3,25 @@ accumulation; scalings, weights and sums in FP64, the pair contraction in
 FP64 (FP32 mode) or FP32 (BF16 / FP16 modes)).
 
 * Per step at fixed walkers and tau: deviation from the FP64 oracle, measured
-  on the scale of the pair terms (mean |pair term|), within a bound set by the
-  operand precision.  In the BF16 / FP16 modes every Green's-function operand
-  (spinor value times sqrt(exp(+-eps tau))) is rounded once to the operand
-  type (the spinor GEMM -- split BF16 when it has a 128x128 tile per CU, FP32
-  below that -- adds at most about 2^-16), and a pair term has
-  degree 8 in the spinor values: bound 8 u for unit roundoff u = 2^-8 (BF16),
-  2^-11 (FP16).  FP32 mode: bound 1e-6 (about 17 u).
-* Over a chain (1000 steps of the 340-spinor workload and of the 980-spinor
-  precision workload): the systematic error -- mean over steps of the paired
-  difference low - FP64 on the same walker trajectory (valid because the
-  walker weights do not depend on the operand precision) -- must stay below
-  1% of the FP64 estimator's blocking standard error.
+  on the scale of the pair terms (mean |pair term|).  The bounds are
+  regression guards, three times the largest deviation measured over the
+  cases below (FP32 3.8e-7 -> bound 1e-6; BF16 3.5e-3 -> 1e-2; FP16
+  1.55e-4 -> 5e-4); they are not a priori error bounds (cancellation inside
+  the Green's-function sums is not bounded on this scale).
+* Over a chain (1000 steps): the systematic error of every result -- the
+  step value, every eps gradient component and fixed random projections of
+  the coefficient gradient -- as the mean over steps of the paired difference
+  low - FP64 on the same walker trajectory (valid because the walker weights
+  do not depend on the operand precision), against the FP64 estimator's
+  blocking standard error sigma_bar.  Where the per-step differences are small
+  enough to resolve a bias of 1% of sigma_bar (|mean diff| + 2 SE(diff) <
+  0.01 sigma_bar): the step value in every mode, the gradients in FP32 mode,
+  and the gradients in FP16 mode on the finite-variance shapes (basis
+  exponents in [0.3, 1.2]).  The BF16 gradients (Green's-function operands
+  rounded to 8 bits) and the gradients of the heavy-tailed full-exponent
+  workloads in the 16-bit modes are noisier per step than that resolution:
+  there the test requires no bias beyond 1% of sigma_bar at three paired
+  standard errors, and prints the measured values.
 * Gradients with low-precision G tiles against the FP64 gradients.
 """
 import numpy as np
@@ -23,12 +30,11 @@ import torch
 
 from gpu_util import dev, requires_gpu
 from oracle import integrand as oi
-from oracle.blocking import blocking
 from oracle.weights import n_g, tau_lambda
 from synth import initial_walkers, make_inputs
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
-BOUND = {"fp32": 1e-6, "bf16": 8 * 2.0 ** -8, "fp16": 8 * 2.0 ** -11}
+BOUND = {"fp32": 1e-6, "bf16": 1e-2, "fp16": 5e-4}
 
 
 def _ctx(inp, **kw):
@@ -67,12 +73,18 @@ def test_low_precision_step_near_oracle(prec, name, over, taus):
         assert err < BOUND[prec]
 
 
-def _chain(name, n_burn, n, delta, key):
-    """One trajectory evaluated in every mode on the same walkers and tau
-    (the walker weights do not depend on the operand precision)."""
+N_PROJ = 8   # fixed random projections Re<D_j, Cbar> of the coefficient gradient
+
+
+def _chain(name, n_burn, n, delta, key, **over):
+    """One trajectory evaluated in every mode, with both gradients, on the same
+    walkers and tau (the walker weights do not depend on the operand
+    precision).  Per mode and step: the step value, the eps gradient and
+    N_PROJ projections of the coefficient gradient onto fixed random
+    directions."""
     from paper_2203_05632_amd import Context
-    inp = make_inputs(name)
-    ctxs = {p: Context.from_inputs(inp, precision=p) for p in ("fp64", "fp32", "bf16", "fp16")}
+    inp = make_inputs(name, **over)
+    ctxs = {p: Context.from_inputs(inp, precision=p, want_grad=True) for p in ("fp64", "fp32", "bf16", "fp16")}
     drv = ctxs["fp64"]
     wk = dev(initial_walkers(inp))
     w = torch.zeros(inp.m, dtype=torch.float64, device="cuda")
@@ -80,13 +92,22 @@ def _chain(name, n_burn, n, delta, key):
     tau = torch.zeros(inp.n_tau, dtype=torch.float64, device="cuda")
     for s in range(n_burn):
         drv.metropolis(wk, w, key, s, delta)
-    hist = {p: torch.zeros((n, inp.n_tau, 3), dtype=torch.float64, device="cuda") for p in ctxs}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    D = torch.randn((N_PROJ, 4 * inp.n_b * inp.n_sp), generator=gen, dtype=torch.float64, device="cuda")
+    e2 = torch.zeros((inp.n_tau, 3), dtype=torch.float64, device="cuda")
+    gc = torch.zeros((2, inp.n_b, inp.n_sp), dtype=torch.complex128, device="cuda")
+    hist = {p: (torch.zeros((n, 1), dtype=torch.float64, device="cuda"),
+                torch.zeros((n, inp.n_sp), dtype=torch.float64, device="cuda"),
+                torch.zeros((n, N_PROJ), dtype=torch.float64, device="cuda")) for p in ctxs}
     for i in range(n):
         drv.advance(wk, w, key, n_burn + i, delta, tau)
         for p, c in ctxs.items():
-            c.step(wk, tau, hist[p][i])
+            v, ge, gp = hist[p]
+            c.step(wk, tau, e2, grad_eps=ge[i], grad_coeffs=gc, value=v[i])
+            torch.mv(D, torch.view_as_real(gc).reshape(-1), out=gp[i])
     torch.cuda.synchronize()
-    return {p: h.mean(dim=1).cpu().numpy()[:, 2] for p, h in hist.items()}
+    return {p: tuple(x.cpu().numpy() for x in h) for p, h in hist.items()}
 
 
 @pytest.fixture(scope="module")
@@ -96,30 +117,59 @@ def chain_runs():
 
 
 @pytest.fixture(scope="module")
+def chain_runs_narrow():
+    """The 340-spinor shapes with basis exponents in [0.3, 1.2], where the
+    estimator has finite variance and sigma_bar settles: 1000 steps."""
+    return _chain("C1", 200, 1000, 0.6, (3, 0), exp_range=(0.3, 1.2))
+
+
+@pytest.fixture(scope="module")
 def chain_runs_c3():
     """The precision workload (980 spinors, m = 256, 1 tau per step): 1000 steps."""
     return _chain("C3", 100, 1000, 0.3, (2, 0))
 
 
-def _check_systematic(runs, prec, label):
-    ref = runs["fp64"]
-    d = runs[prec] - ref
-    _, sbar = blocking(ref, 100)
-    mean_d = float(d.mean())
-    _, se_d = blocking(d, 100)
-    print(f"{label} {prec}: systematic {mean_d:.3e} +- {se_d:.3e}, sigma_bar(FP64) {sbar:.3e}, "
-          f"ratio {abs(mean_d) / sbar:.2e}", flush=True)
-    assert abs(mean_d) < 0.01 * sbar
+def _systematic(x, y):
+    """(|mean(y - x)| / sigma_bar(x), SE(y - x) / sigma_bar(x)) per observable
+    (columns), by blocking with N_b = 100."""
+    from paper_2203_05632_amd import blocking_sigma
+    d = y - x
+    s = blocking_sigma(x, 100)
+    return np.abs(d.mean(axis=0)) / s, blocking_sigma(d, 100) / s
+
+
+def _check_systematic(runs, prec, label, resolved_grad):
+    """Systematic error stated per result: the step value, every eps gradient
+    component and every coefficient-gradient projection.  Resolved results:
+    |mean diff| + 2 SE(diff) < 0.01 sigma_bar.  Gradients not resolved at that
+    level: |mean diff| < 0.01 sigma_bar + 3 SE(diff)."""
+    ref, low = runs["fp64"], runs[prec]
+    for name, x, y in zip(("value", "grad_eps", "grad_coeffs_proj"), ref, low):
+        r, se = _systematic(x, y)
+        bound = r + 2.0 * se
+        j = int(np.argmax(bound))
+        print(f"{label} {prec} {name}: max |mean diff| / sigma_bar = {r.max():.3e}, at the max of "
+              f"(|mean diff| + 2 SE) / sigma_bar = {bound[j]:.3e}: |mean diff| {r[j]:.3e}, SE {se[j]:.3e} "
+              f"({bound.size} components, median {np.median(bound):.2e})", flush=True)
+        if name == "value" or resolved_grad:
+            assert bound.max() < 0.01, name
+        else:
+            assert np.all(r < 0.01 + 3.0 * se), name
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_systematic_error_below_one_percent_of_sigma(chain_runs, prec):
-    _check_systematic(chain_runs, prec, "C1")
+    _check_systematic(chain_runs, prec, "C1", prec == "fp32")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_systematic_error_below_one_percent_of_sigma_finite_variance(chain_runs_narrow, prec):
+    _check_systematic(chain_runs_narrow, prec, "C1 exponents [0.3, 1.2]", prec != "bf16")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_systematic_error_below_one_percent_of_sigma_precision_workload(chain_runs_c3, prec):
-    _check_systematic(chain_runs_c3, prec, "C3")
+    _check_systematic(chain_runs_c3, prec, "C3", prec == "fp32")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
