@@ -21,8 +21,28 @@ namespace {
 
 constexpr int GKC = 16;  // rows y of H (and of psi) per LDS chunk
 
-// grid: (column tiles of 32 spinors: occupied tiles first, then virtual;
-//        R / 32 row tiles).  4 waves: 16x16 output sub-tiles (wx, wk).
+// Work items: (row tile of 32 rows x, column tile of 32 spinors: occupied
+// tiles first, then virtual), in groups of kRowGroup row tiles; within a
+// group, column-major, so that consecutive items share H row panels and psi
+// column panels.  Block b runs on XCD b % 8, and each XCD takes a contiguous
+// range of items: the blocks resident on one XCD at a time cover a few row
+// panels x a few column panels and share them through that XCD's L2.
+constexpr int kRowGroup = 8;
+
+__device__ inline bool grad_item(int n_rt, int n_ct, int &rt, int &ct) {
+    const int n_items = n_rt * n_ct, per = (n_items + 7) / 8;
+    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= n_items) return false;
+    const int g = item / (kRowGroup * n_ct);
+    const int rows = min(kRowGroup, n_rt - g * kRowGroup);
+    const int w = item - g * kRowGroup * n_ct;
+    ct = w / rows;
+    rt = g * kRowGroup + w % rows;
+    return true;
+}
+
+// grid: 8 ceil(n_rt n_ct / 8) blocks over the work items above (n_rt = R / 32
+// row tiles, n_ct column tiles).  4 waves: 16x16 output sub-tiles (wx, wk).
 // Psibar[k][x] = sum_t s_t[k] sum_y H_t[x][y] psi[k][y]; the partial
 // epsbar of this row tile goes to eps_part[row tile][k].  The complex
 // products take three real MFMA products (3M / Gauss form): for
@@ -37,19 +57,21 @@ template <int NT, typename P>
 __global__ __launch_bounds__(256) void grad_gemm_kernel(
     const double2 *__restrict__ Hm, const double2 *__restrict__ Hp, const P *__restrict__ psi,
     const double *__restrict__ scale, const double *__restrict__ tau, int t0, int R, int no, int nsp, int n_occ_tiles,
-    bool accumulate, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
+    int n_col_tiles, bool accumulate, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
     __shared__ double2 pa[2][NT][GKC][32];  // H_t chunk: [y][x], x fastest
     __shared__ double2 pb[2][GKC][32];      // psi chunk: [y][k], k fastest
     __shared__ double esum[2][32];
+    int rt, ct;
+    if (!grad_item(R / 32, n_col_tiles, rt, ct)) return;  // padding block (the whole block)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wx = wave >> 1, wk = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
-    const bool occ = (int)blockIdx.x < n_occ_tiles;
-    const int k0 = occ ? 32 * blockIdx.x : no + 32 * (blockIdx.x - n_occ_tiles);
+    const bool occ = ct < n_occ_tiles;
+    const int k0 = occ ? 32 * ct : no + 32 * (ct - n_occ_tiles);
     const int k_hi = occ ? no : nsp;
     const double sign = occ ? 1.0 : -1.0;
     const double2 *H = occ ? Hm : Hp;
-    const int x0 = 32 * blockIdx.y;
+    const int x0 = 32 * rt;
     const size_t RR = (size_t)R * R;
 
     // this lane's column k and its scalings s_t[k]
@@ -139,7 +161,7 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
     if (lk == 0) esum[wx][16 * wk + li] = e_acc;
     __syncthreads();
     if (tid < 32 && k0 + tid < k_hi) {
-        double *o = eps_part + (size_t)blockIdx.y * nsp + k0 + tid;
+        double *o = eps_part + (size_t)rt * nsp + k0 + tid;
         const double v = esum[0][tid] + esum[1][tid];
         *o = accumulate ? *o + v : v;
     }
@@ -346,17 +368,18 @@ hipError_t launch_grad_gemm(const mcmp2_ctx *c, const double *tau, int n_tau, in
     const double2 *Hm = reinterpret_cast<const double2 *>(c->Hm), *Hp = reinterpret_cast<const double2 *>(c->Hp);
     const P *psi = reinterpret_cast<const P *>(c->psi);
     double2 *psibar = reinterpret_cast<double2 *>(c->psibar);
-    dim3 grid(n_occ_tiles + n_vir_tiles, c->R / 32);
+    const int n_ct = n_occ_tiles + n_vir_tiles;
+    const int grid = 8 * ((c->R / 32 * n_ct + 7) / 8);
     for (int t0 = 0; t0 < n_tau; t0 += 2) {
         const int nt = std::min(2, n_tau - t0);
         const bool acc = t0 > 0;
         const int ps = prof_begin(c, MCMP2_K_ADJ_GEMM);
         if (nt == 2)
             grad_gemm_kernel<2, P><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
-                                                                n_occ_tiles, acc, psibar, c->eps_part);
+                                                                n_occ_tiles, n_ct, acc, psibar, c->eps_part);
         else
             grad_gemm_kernel<1, P><<<grid, 256, 0, c->stream>>>(Hm, Hp, psi, c->scale, tau, t0, c->R, c->no, c->nsp,
-                                                                n_occ_tiles, acc, psibar, c->eps_part);
+                                                                n_occ_tiles, n_ct, acc, psibar, c->eps_part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if ((e = prof_end(c, ps, MCMP2_K_ADJ_GEMM)) != hipSuccess) return e;
