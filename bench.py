@@ -544,8 +544,9 @@ def study_convergence(args):
                              ("C1", "3 nuclei, 200 L / 460 S primitives, 40 occupied / 300 virtual spinors, 2 tau",
                               None)):
         rows = []
+        base = make_inputs(wl, exp_range=FINITE_VARIANCE_EXPONENTS)
         for m in (8, 16, 32, 64, 128, 256, 512):
-            inp = make_inputs(wl, m=m, exp_range=FINITE_VARIANCE_EXPONENTS)
+            inp = base.with_(m=m)
             state = burn_in(inp, initial_walkers(inp), (1, m), 300)
             el, vals = replay_values(inp, "fp64", state, K)
             curve = []
@@ -571,7 +572,9 @@ def study_scaling(args):
     basis functions and of electrons).  Two synthetic ladders on the
     three-nucleus shapes with basis exponents in [0.3, 1.2], one tau per step:
       n_bas: (s, p, d) shells x 4 ... 60 (40 ... 600 L primitives), 20
-             occupied spinors, 2 n_L - 20 virtual (all positive-energy spinors);
+             occupied spinors, n_L - 20 virtual (as many spinors as L
+             primitives: the narrow exponent range leaves the basis too close
+             to linear dependence for 2 n_L);
       n_occ: the 200-primitive L set, n_occ = 4 ... 120 occupied of 400 spinors.
     For m = 8 and 12 (the paper's) and 128, 512, FP64 (and BF16 at 512):
     time per step t, the per-step variance v = sigma_bar_N^2 N (blocking,
@@ -584,7 +587,7 @@ def study_scaling(args):
     from synth import initial_walkers, make_inputs
     runs = [(8, "fp64", 2000), (12, "fp64", 2000), (128, "fp64", 1000), (512, "fp64", 1000), (512, "bf16", 1000)]
     ladders = {
-        "n_bas": [dict(shell_reps=r, n_occ=20, n_vir=20 * r - 20) for r in (4, 8, 12, 20, 40, 60)],
+        "n_bas": [dict(shell_reps=r, n_occ=20, n_vir=10 * r - 20) for r in (4, 8, 12, 20, 40, 60)],
         "n_occ": [dict(n_occ=o, n_vir=400 - o) for o in (4, 10, 20, 40, 80, 120)],
     }
     out = {"study": "time to sigma_bar/|E2| = 0.1 vs basis size and occupied count", "n_b": 100,
@@ -596,7 +599,7 @@ def study_scaling(args):
             row = {"n_L": base.n_L, "n_S": base.n_S, "n_b": base.n_b, "n_occ": base.n_occ, "n_vir": base.n_vir,
                    "runs": {}}
             for m, prec, K in runs:
-                inp = make_inputs("C1", exp_range=FINITE_VARIANCE_EXPONENTS, n_tau=1, m=m, **kw)
+                inp = base.with_(m=m)
                 state = burn_in(inp, initial_walkers(inp), (2, m), 300)
                 el, vals = replay_values(inp, prec, state, K)
                 sb = float(blocking_sigma(vals[:, 2], 100))

@@ -64,21 +64,23 @@ __global__ __launch_bounds__(256) void adj_operands_kernel(const float2 *__restr
     }
 }
 
-// One block: rows [x0, x0 + 128) x spinor columns [k0, k0 + 2 WN) of one
-// kind (occupied: A = H-, virtual: A = H+).  Waves (wr, wc) own 64 rows x WN
-// columns; the lane's 16x16 sub-tiles (i, j) hold rows x0 + 64 wr + 16 i +
-// 4 (l / 16) + v and column k0 + WN wc + 16 j + l % 16 in element v.
+// One block: rows [x0, x0 + 128) x spinor columns [k0, k0 + NCW WN) of one
+// kind (occupied: A = H-, virtual: A = H+), 2 x NCW waves.  Waves (wr, wc)
+// own 64 rows x WN columns; the lane's 16x16 sub-tiles (i, j) hold rows
+// x0 + 64 wr + 16 i + 4 (l / 16) + v and column k0 + WN wc + 16 j + l % 16 in
+// element v.  Wider blocks (NCW = 4) read each H row panel for twice the
+// columns, halving the H traffic per flop.
 // Work items (row tile, column tile), row-tile major, are dealt to the XCDs
 // in contiguous ranges (block b runs on XCD b % 8), so that blocks sharing
 // H rows or V columns run side by side on one L2.
-template <int WN>
-__global__ __launch_bounds__(256) void adj_lp_kernel(
+template <int WN, int NCW, int STAGES>
+__global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     const uint32_t *__restrict__ Hm, const uint32_t *__restrict__ Hp, const uint32_t *__restrict__ V,
     const float2 *__restrict__ psi, const double *__restrict__ tau, int n_tau, int R, int no, int nsp,
     int n_occ_tiles, int n_col_tiles, int n_items, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
-    constexpr int BN = 2 * WN, NJ = WN / 16;
-    constexpr int NA = ABM * (AK / 4) / 256;  // 16-byte A units per thread per chunk
-    constexpr int NB = BN * (AK / 4) / 256;   // 16-byte B units per thread per chunk
+    constexpr int NTH = 128 * NCW, BN = NCW * WN, NJ = WN / 16;
+    constexpr int NA = ABM * (AK / 4) / NTH;  // 16-byte A units per thread per chunk
+    constexpr int NB = BN * (AK / 4) / NTH;   // 16-byte B units per thread per chunk
     __shared__ __align__(16) uint32_t lds[2][(ABM + BN) * AK];
     __shared__ float dpart[2][BN];
 
@@ -92,36 +94,36 @@ __global__ __launch_bounds__(256) void adj_lp_kernel(
     const uint32_t *H = occ ? Hm : Hp;
     const int x0 = ABM * rt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+    const int wr = wave / NCW, wc = wave % NCW, li = lane & 15, lk = lane >> 4;
 
-    // global -> register staging: unit u = tid + 256 j covers row u / 8, words 4 (u % 8) .. + 3
+    // global -> register staging: unit u = tid + NTH j covers row u / 8, words 4 (u % 8) .. + 3
     const uint32_t *asrc[NA];
     const uint32_t *bsrc[NB];
     for (int j = 0; j < NA; ++j) {
-        const int u = tid + 256 * j;
+        const int u = tid + NTH * j;
         asrc[j] = H + (size_t)min(x0 + u / 8, R - 1) * R + 4 * (u % 8);
     }
     for (int j = 0; j < NB; ++j) {
-        const int u = tid + 256 * j;
+        const int u = tid + NTH * j;
         bsrc[j] = V + (size_t)min(k0 + u / 8, k_hi - 1) * R + 4 * (u % 8);
     }
     const size_t RR = (size_t)R * R, NR = (size_t)nsp * R;
     const int cpt = R / AK;  // chunks per tau sample
     const int n_chunks = n_tau * cpt;
     u32x4 ra[NA], rb[NB];
-    auto gload = [&](int c) {
+    auto gload = [&](u32x4(&xa)[NA], u32x4(&xb)[NB], int c) __attribute__((always_inline)) {
         const int t = c / cpt, y0 = (c % cpt) * AK;
-        for (int j = 0; j < NA; ++j) ra[j] = *reinterpret_cast<const u32x4 *>(asrc[j] + t * RR + y0);
-        for (int j = 0; j < NB; ++j) rb[j] = *reinterpret_cast<const u32x4 *>(bsrc[j] + t * NR + y0);
+        for (int j = 0; j < NA; ++j) xa[j] = *reinterpret_cast<const u32x4 *>(asrc[j] + t * RR + y0);
+        for (int j = 0; j < NB; ++j) xb[j] = *reinterpret_cast<const u32x4 *>(bsrc[j] + t * NR + y0);
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](const u32x4(&xa)[NA], const u32x4(&xb)[NB], int buf) __attribute__((always_inline)) {
         for (int j = 0; j < NA; ++j) {
-            const int u = tid + 256 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf][4 * swz(u / 8, u % 8)]) = ra[j];
+            const int u = tid + NTH * j;
+            *reinterpret_cast<u32x4 *>(&lds[buf][4 * swz(u / 8, u % 8)]) = xa[j];
         }
         for (int j = 0; j < NB; ++j) {
-            const int u = tid + 256 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf][4 * swz(ABM + u / 8, u % 8)]) = rb[j];
+            const int u = tid + NTH * j;
+            *reinterpret_cast<u32x4 *>(&lds[buf][4 * swz(ABM + u / 8, u % 8)]) = xb[j];
         }
     };
 
@@ -131,12 +133,7 @@ __global__ __launch_bounds__(256) void adj_lp_kernel(
     double d_prev = 0.0, e_acc = 0.0;  // threads tid < BN: column k0 + tid
     const double sgn = occ ? 0.5 : -0.5;
 
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int c = 0; c < n_chunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < n_chunks) gload(c + 1);
+    auto compute = [&](int buf) __attribute__((always_inline)) {
         const uint32_t *l = lds[buf];
 #pragma unroll
         for (int ks = 0; ks < AK / 4; ks += 4) {  // 16-byte units: lane group lk reads unit ks + lk
@@ -159,34 +156,70 @@ __global__ __launch_bounds__(256) void adj_lp_kernel(
                 }
             }
         }
-        if (c + 1 < n_chunks) lstore(buf ^ 1);
-        if ((c + 1) % cpt == 0) {
-            // tau boundary: D_t[k] over this block's rows from the running sums
-            const int t = c / cpt;
-            for (int j = 0; j < NJ; ++j) {
-                const int k = k0 + WN * wc + 16 * j + li;
-                float d = 0.f;
-                if (k < k_hi)
-                    for (int i = 0; i < 4; ++i) {
-                        const int xb = x0 + 64 * wr + 16 * i + 4 * lk;
-                        for (int v = 0; v < 4; ++v)
-                            if (xb + v < R) {
-                                const float2 p = psi[(size_t)k * R + xb + v];
-                                d += p.x * pre[i][j][v] + p.y * pim[i][j][v];
-                            }
-                    }
-                d += __shfl_xor(d, 16, 64);
-                d += __shfl_xor(d, 32, 64);
-                if (lk == 0) dpart[wr][WN * wc + 16 * j + li] = d;
-            }
-            __syncthreads();
-            if (tid < BN) {
-                const double D = (double)dpart[0][tid] + (double)dpart[1][tid];
-                e_acc += sgn * tau[t] * (D - d_prev);
-                d_prev = D;
-            }
+    };
+    // after chunk c: at a tau boundary, D_t[k] over this block's rows from the running sums
+    auto tau_boundary = [&](int c) __attribute__((always_inline)) {
+        if ((c + 1) % cpt != 0) return;
+        const int t = c / cpt;
+        for (int j = 0; j < NJ; ++j) {
+            const int k = k0 + WN * wc + 16 * j + li;
+            float d = 0.f;
+            if (k < k_hi)
+                for (int i = 0; i < 4; ++i) {
+                    const int xb = x0 + 64 * wr + 16 * i + 4 * lk;
+                    for (int v = 0; v < 4; ++v)
+                        if (xb + v < R) {
+                            const float2 p = psi[(size_t)k * R + xb + v];
+                            d += p.x * pre[i][j][v] + p.y * pim[i][j][v];
+                        }
+                }
+            d += __shfl_xor(d, 16, 64);
+            d += __shfl_xor(d, 32, 64);
+            if (lk == 0) dpart[wr][WN * wc + 16 * j + li] = d;
         }
         __syncthreads();
+        if (tid < BN) {
+            const double D = (double)dpart[0][tid] + (double)dpart[1][tid];
+            e_acc += sgn * tau[t] * (D - d_prev);
+            d_prev = D;
+        }
+    };
+
+    if constexpr (STAGES == 1) {
+        gload(ra, rb, 0);
+        lstore(ra, rb, 0);
+        __syncthreads();
+        for (int c = 0; c < n_chunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < n_chunks) gload(ra, rb, c + 1);
+            compute(buf);
+            if (c + 1 < n_chunks) lstore(ra, rb, buf ^ 1);
+            tau_boundary(c);
+            __syncthreads();
+        }
+    } else {
+        // two register stages: the loads of chunk c + 2 are issued while chunk
+        // c is multiplied and chunk c + 1 (loaded one chunk earlier) goes to
+        // LDS; past the last chunk the loads re-read it (branch-free)
+        u32x4 ra2[NA], rb2[NB];
+        auto at = [&](int c) { return min(c, n_chunks - 1); };
+        gload(ra, rb, 0);
+        gload(ra2, rb2, at(1));
+        lstore(ra, rb, 0);
+        __syncthreads();
+        for (int c = 0; c < n_chunks; c += 2) {
+            gload(ra, rb, at(c + 2));
+            compute(0);
+            if (c + 1 < n_chunks) lstore(ra2, rb2, 1);
+            tau_boundary(c);
+            __syncthreads();
+            if (c + 1 >= n_chunks) break;
+            gload(ra2, rb2, at(c + 3));
+            compute(1);
+            if (c + 2 < n_chunks) lstore(ra, rb, 0);
+            tau_boundary(c + 1);
+            __syncthreads();
+        }
     }
 
     for (int j = 0; j < NJ; ++j) {
@@ -201,16 +234,16 @@ __global__ __launch_bounds__(256) void adj_lp_kernel(
     if (tid < BN && k0 + tid < k_hi) eps_part[(size_t)rt * nsp + k0 + tid] = e_acc;
 }
 
-template <int WN>
+template <int WN, int NCW>
 hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
-    constexpr int BN = 2 * WN;
+    constexpr int BN = NCW * WN;
     const int n_occ_tiles = (c->no + BN - 1) / BN, n_vir_tiles = (c->nsp - c->no + BN - 1) / BN;
     const int n_col_tiles = n_occ_tiles + n_vir_tiles;
     const int n_row_tiles = (c->R + ABM - 1) / ABM;
     const int n_items = n_row_tiles * n_col_tiles;
     const int per = (n_items + 7) / 8;
     const int ps = prof_begin(c, MCMP2_K_ADJ_GEMM);
-    adj_lp_kernel<WN><<<8 * per, 256, 0, c->stream>>>(
+    adj_lp_kernel<WN, NCW, NCW == 4 ? 2 : 1><<<8 * per, 128 * NCW, 0, c->stream>>>(
         reinterpret_cast<const uint32_t *>(c->Hm), reinterpret_cast<const uint32_t *>(c->Hp), c->Vt,
         reinterpret_cast<const float2 *>(c->psi), tau, n_tau, c->R, c->no, c->nsp, n_occ_tiles, n_col_tiles, n_items,
         reinterpret_cast<double2 *>(c->psibar), c->eps_part);
@@ -233,5 +266,7 @@ hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau) {
     // 416 tiles, 1028 us against 1186 us with 64-column tiles); below that the
     // narrower tiles' extra blocks win (128 pairs: 32 tiles, 101 against 67 us)
     const int wide_items = ((c->R + ABM - 1) / ABM) * ((c->no + 127) / 128 + (c->nsp - c->no + 127) / 128);
-    return wide_items >= c->n_cu ? launch_adj_typed<64>(c, tau, n_tau) : launch_adj_typed<32>(c, tau, n_tau);
+    const int wider_items = ((c->R + ABM - 1) / ABM) * ((c->no + 255) / 256 + (c->nsp - c->no + 255) / 256);
+    if (4 * wider_items >= 3 * c->n_cu) return launch_adj_typed<64, 4>(c, tau, n_tau);
+    return wide_items >= c->n_cu ? launch_adj_typed<64, 2>(c, tau, n_tau) : launch_adj_typed<32, 2>(c, tau, n_tau);
 }
