@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void adj_operands_kernel(const float2 *__restr
 // Work items (row tile, column tile), row-tile major, are dealt to the XCDs
 // in contiguous ranges (block b runs on XCD b % 8), so that blocks sharing
 // H rows or V columns run side by side on one L2.
-template <int WN, int NCW, int STAGES>
+template <int WN, int NCW>
 __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     const uint32_t *__restrict__ Hm, const uint32_t *__restrict__ Hp, const uint32_t *__restrict__ V,
     const float2 *__restrict__ psi, const double *__restrict__ tau, int n_tau, int R, int no, int nsp,
@@ -185,41 +185,16 @@ __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
         }
     };
 
-    if constexpr (STAGES == 1) {
-        gload(ra, rb, 0);
-        lstore(ra, rb, 0);
+    gload(ra, rb, 0);
+    lstore(ra, rb, 0);
+    __syncthreads();
+    for (int c = 0; c < n_chunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < n_chunks) gload(ra, rb, c + 1);
+        compute(buf);
+        if (c + 1 < n_chunks) lstore(ra, rb, buf ^ 1);
+        tau_boundary(c);
         __syncthreads();
-        for (int c = 0; c < n_chunks; ++c) {
-            const int buf = c & 1;
-            if (c + 1 < n_chunks) gload(ra, rb, c + 1);
-            compute(buf);
-            if (c + 1 < n_chunks) lstore(ra, rb, buf ^ 1);
-            tau_boundary(c);
-            __syncthreads();
-        }
-    } else {
-        // two register stages: the loads of chunk c + 2 are issued while chunk
-        // c is multiplied and chunk c + 1 (loaded one chunk earlier) goes to
-        // LDS; past the last chunk the loads re-read it (branch-free)
-        u32x4 ra2[NA], rb2[NB];
-        auto at = [&](int c) { return min(c, n_chunks - 1); };
-        gload(ra, rb, 0);
-        gload(ra2, rb2, at(1));
-        lstore(ra, rb, 0);
-        __syncthreads();
-        for (int c = 0; c < n_chunks; c += 2) {
-            gload(ra, rb, at(c + 2));
-            compute(0);
-            if (c + 1 < n_chunks) lstore(ra2, rb2, 1);
-            tau_boundary(c);
-            __syncthreads();
-            if (c + 1 >= n_chunks) break;
-            gload(ra2, rb2, at(c + 3));
-            compute(1);
-            if (c + 2 < n_chunks) lstore(ra, rb, 0);
-            tau_boundary(c + 1);
-            __syncthreads();
-        }
     }
 
     for (int j = 0; j < NJ; ++j) {
@@ -243,7 +218,7 @@ hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
     const int n_items = n_row_tiles * n_col_tiles;
     const int per = (n_items + 7) / 8;
     const int ps = prof_begin(c, MCMP2_K_ADJ_GEMM);
-    adj_lp_kernel<WN, NCW, NCW == 4 ? 2 : 1><<<8 * per, 128 * NCW, 0, c->stream>>>(
+    adj_lp_kernel<WN, NCW><<<8 * per, 128 * NCW, 0, c->stream>>>(
         reinterpret_cast<const uint32_t *>(c->Hm), reinterpret_cast<const uint32_t *>(c->Hp), c->Vt,
         reinterpret_cast<const float2 *>(c->psi), tau, n_tau, c->R, c->no, c->nsp, n_occ_tiles, n_col_tiles, n_items,
         reinterpret_cast<double2 *>(c->psibar), c->eps_part);

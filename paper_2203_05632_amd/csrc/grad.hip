@@ -20,6 +20,7 @@
 namespace {
 
 constexpr int GKC = 16;  // rows y of H (and of psi) per LDS chunk
+constexpr int kPadRow = 33;  // LDS row length (double2) of the 32-wide chunks
 
 // Work items: (row tile of 32 rows x, column tile of 32 spinors: occupied
 // tiles first, then virtual), in groups of kRowGroup row tiles; within a
@@ -58,8 +59,11 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
     const double2 *__restrict__ Hm, const double2 *__restrict__ Hp, const P *__restrict__ psi,
     const double *__restrict__ scale, const double *__restrict__ tau, int t0, int R, int no, int nsp, int n_occ_tiles,
     int n_col_tiles, bool accumulate, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
-    __shared__ double2 pa[2][NT][GKC][32];  // H_t chunk: [y][x], x fastest
-    __shared__ double2 pb[2][GKC][32];      // psi chunk: [y][k], k fastest
+    // H_t chunk [y][x] and psi chunk [y][k], rows padded to 33 entries (528 B):
+    // the staging stores run down a column (16 lanes, consecutive y), which
+    // with 512-byte rows would all hit the same four banks
+    __shared__ double2 pa[2][NT][GKC][kPadRow];
+    __shared__ double2 pb[2][GKC][kPadRow];
     __shared__ double esum[2][32];
     int rt, ct;
     if (!grad_item(R / 32, n_col_tiles, rt, ct)) return;  // padding block (the whole block)

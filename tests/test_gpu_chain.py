@@ -131,3 +131,28 @@ def test_run_directory_resume_after_a_stop(tmp_path, grad):
     assert recs_a == recs_c
     assert recs_a[-1]["I_N"] == [float(v) for v in ra.mean]
     assert 0.0 < recs_a[-1]["acceptance"] < 1.0
+
+
+def test_gpu_chain_mean_within_three_sigma_of_deterministic_mp2():
+    """The whole estimator on the GPU (Metropolis walk, tau sampling, every
+    kernel of the step) against Eq. FinalMP2: on the tiny two-nucleus system
+    with basis exponents in [0.3, 1.2] (finite variance), 64 walker pairs,
+    6000 steps after 300 of burn-in, the direct and exchange parts and the
+    total lie within 3 blocking standard errors of the deterministic values
+    stored in tests/golden/c0_narrow_e2.json (written from the oracle's
+    McMurchie-Davidson integrals and four-index transformation)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c0_narrow_e2.json")) as fh:
+        ref = json.load(fh)
+    inp = make_inputs("C0", exp_range=(0.3, 1.2), m=64)
+    ch = _chain(inp, key=(11, 0))
+    ch.burn_in(300)
+    ch.run(6000, block=100)
+    res = ch.result()
+    for col, name in enumerate(("direct", "exchange", "total")):
+        z = (res.mean[col] - ref[name]) / res.sigma[col]
+        print(f"{name}: {res.mean[col]:.6f} +- {res.sigma[col]:.6f} (deterministic {ref[name]:.6f}, z = {z:+.2f})",
+              flush=True)
+        assert abs(z) < 3.0
+        assert res.sigma[col] < 0.2 * abs(ref[name])   # the check has power
