@@ -39,31 +39,6 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, 
 // the SQ_LDS_BANK_CONFLICT counter; padded 144-byte rows do conflict).
 __device__ inline int swz(int row, int unit) { return row * 8 + (unit ^ (row & 7)); }
 
-// psi (float2 [nsp][R]) times s_t[k] -> V_t[k][y] as packed BF16 pairs.
-// Four consecutive y per thread (R is a multiple of 4, so they share k):
-// 32-byte loads, 16-byte stores per tau sample.
-__global__ __launch_bounds__(256) void adj_operands_kernel(const float2 *__restrict__ psi,
-                                                           const double *__restrict__ scale, int R, int nsp,
-                                                           int n_tau, uint32_t *__restrict__ V) {
-    const size_t n = (size_t)nsp * R;
-    const size_t i = 4 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= n) return;
-    const int k = (int)(i / R);
-    const f4v p01 = *reinterpret_cast<const f4v *>(psi + i), p23 = *reinterpret_cast<const f4v *>(psi + i + 2);
-    const float re[4] = {p01[0], p01[2], p23[0], p23[2]}, im[4] = {p01[1], p01[3], p23[1], p23[3]};
-    for (int t = 0; t < n_tau; ++t) {
-        const double s = scale[(size_t)t * nsp + k];
-        u32x4 o;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const __bf16 r = (__bf16)(float)((double)re[q] * s), m = (__bf16)(float)((double)im[q] * s);
-            o[q] = (uint32_t)__builtin_bit_cast(unsigned short, r) |
-                   ((uint32_t)__builtin_bit_cast(unsigned short, m) << 16);
-        }
-        *reinterpret_cast<u32x4 *>(V + (size_t)t * n + i) = o;
-    }
-}
-
 // One block: rows [x0, x0 + 128) x spinor columns [k0, k0 + NCW WN) of one
 // kind (occupied: A = H-, virtual: A = H+), 2 x NCW waves.  Waves (wr, wc)
 // own 64 rows x WN columns; the lane's 16x16 sub-tiles (i, j) hold rows
@@ -231,12 +206,9 @@ hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
 
 int adjoint_lp_row_tiles(const mcmp2_ctx *c) { return (c->R + ABM - 1) / ABM; }
 
+// V_t (psi s_t as packed BF16 pairs) was written by the operand kernel of the
+// Green's functions in the same step (green_lp.hip).
 hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau) {
-    const size_t n = (size_t)c->nsp * c->R;
-    adj_operands_kernel<<<(unsigned)((n / 4 + 255) / 256), 256, 0, c->stream>>>(
-        reinterpret_cast<const float2 *>(c->psi), c->scale, c->R, c->nsp, n_tau, c->Vt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     // 128-column tiles once they give every CU a block (the 512-pair workload:
     // 416 tiles, 1028 us against 1186 us with 64-column tiles); below that the
     // narrower tiles' extra blocks win (128 pairs: 32 tiles, 101 against 67 us)

@@ -62,13 +62,16 @@ __device__ inline uint32_t pack_op(double re, double im) {
 // grid (R / 64, ceil(nsp / 32), ceil(n_tau / tpb)); psi float2 [nsp][R] ->
 // U_t [R][Ktot] for tpb tau samples per block from one LDS copy of the
 // block's psi tile (tpb = n_tau when the first two grid dimensions alone
-// give every CU several blocks, else 1).
+// give every CU several blocks, else 1).  With gradients (V set) the same
+// tile also gives the adjoint GEMM's operand V_t[k][row] = psi s_t[k] as
+// packed BF16 pairs (see adjoint_lp.hip).
 template <typename T>
 __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restrict__ psi,
                                                           const double *__restrict__ scale, int R, int nsp, int no,
-                                                          int Ko, int Ktot, int n_tau, int tpb, T *__restrict__ U) {
+                                                          int Ko, int Ktot, int n_tau, int tpb, T *__restrict__ U,
+                                                          uint32_t *__restrict__ V) {
     __shared__ float2 tile[32][65];
-    __shared__ double sq[32];
+    __shared__ double sq[32], sf[32];
     const int r0 = 64 * blockIdx.x, k0 = 32 * blockIdx.y;
     const int t_lo = tpb * (int)blockIdx.z, t_hi = min(n_tau, t_lo + tpb);
     const int tid = threadIdx.x;
@@ -80,7 +83,8 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
         if (t > t_lo) __syncthreads();  // sq of the previous tau sample has been used
         if (tid < 32) {
             const int k = k0 + tid;
-            sq[tid] = k < nsp ? sqrt(scale[(size_t)t * nsp + k]) : 0.0;
+            sf[tid] = k < nsp ? scale[(size_t)t * nsp + k] : 0.0;
+            sq[tid] = sqrt(sf[tid]);
         }
         __syncthreads();
         T *Ut = U + (size_t)t * R * Ktot;
@@ -91,6 +95,17 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
             const float2 v = tile[kk][r];
             *reinterpret_cast<uint32_t *>(Ut + (size_t)(r0 + r) * Ktot + K) =
                 pack_op<T>((double)v.x * sq[kk], (double)v.y * sq[kk]);
+        }
+        if (V) {
+            uint32_t *Vt = V + (size_t)t * nsp * R;
+            for (int e = tid; e < 32 * 64; e += 256) {  // coalesced along rows
+                const int kk = e >> 6, r = e & 63, k = k0 + kk;
+                if (k >= nsp) continue;
+                const float2 v = tile[kk][r];
+                const __bf16 re = (__bf16)(float)((double)v.x * sf[kk]), im = (__bf16)(float)((double)v.y * sf[kk]);
+                Vt[(size_t)k * R + r0 + r] = (uint32_t)__builtin_bit_cast(unsigned short, re) |
+                                             ((uint32_t)__builtin_bit_cast(unsigned short, im) << 16);
+            }
         }
     }
 }
@@ -429,7 +444,8 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     const int tpb = bx * by >= 4 * c->n_cu ? n_tau : 1;
     dim3 g(bx, by, (n_tau + tpb - 1) / tpb);
     lp_operands_kernel<T><<<g, 256, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->psi), c->scale, c->R,
-                                                    c->nsp, c->no, c->Ko, c->Ktot, n_tau, tpb, U);
+                                                    c->nsp, c->no, c->Ko, c->Ktot, n_tau, tpb, U,
+                                                    grad ? c->Vt : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (sizeof(T) == 2)

@@ -114,6 +114,79 @@ __device__ __attribute__((always_inline)) inline void lp_gemm_tile(const T *__re
     }
 }
 
+// One 128 x 128 tile of the split product D = A_hi B_hi^T + A_hi B_lo^T +
+// A_lo B_hi^T over K in [0, K) (K a multiple of 32), the hi and lo parts of
+// each operand row sitting at element offsets (a_hi, a_lo), (b_hi, b_lo) of
+// that row.  A stage holds 32 K values of each part side by side in one
+// 128-byte LDS row (units 0-3 hi, 4-7 lo), so one K step reads four
+// fragment sets for 48 MFMAs (the tripled-K form reads six for 48).  Layout
+// of acc as in lp_gemm_tile.
+__device__ __attribute__((always_inline)) inline void lp_split_tile(const __bf16 *__restrict__ A, int lda, int a_row0,
+                                                                    int a_rows, int a_hi, int a_lo,
+                                                                    const __bf16 *__restrict__ B, int ldb, int b_row0,
+                                                                    int b_rows, int b_hi, int b_lo, int K,
+                                                                    uint32_t *lds, f4v (&acc)[4][4]) {
+    constexpr int STAGE = 2 * LBM * LKW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+    // staging unit u = tid + 256 j (j < 8): stage row u / 8 (A rows, then B rows), unit u % 8
+    const uint32_t *src[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int u = tid + 256 * j, row = u >> 3, unit = u & 7;
+        const bool a = row < LBM;
+        const __bf16 *p = a ? A + (size_t)min(a_row0 + row, a_rows - 1) * lda
+                            : B + (size_t)min(b_row0 + row - LBM, b_rows - 1) * ldb;
+        const int off = unit < 4 ? (a ? a_hi : b_hi) + 8 * unit : (a ? a_lo : b_lo) + 8 * (unit - 4);
+        src[j] = reinterpret_cast<const uint32_t *>(p + off);
+    }
+    u32x4 rg[8];
+    auto gload = [&](int w0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rg[j] = *reinterpret_cast<const u32x4 *>(src[j] + w0);
+    };
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int u = tid + 256 * j;
+            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + 4 * swz(u >> 3, u & 7)]) = rg[j];
+        }
+    };
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int n = K / 32;
+    if (n == 0) return;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < n) gload((c + 1) * 16);  // 32 K values = 16 words per part
+        const uint32_t *l = &lds[buf * STAGE];
+        u32x4 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ah[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, lk));
+            al[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, 4 + lk));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            bh[j] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(LBM + 64 * wc + 16 * j + li, lk));
+            bl[j] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(LBM + 64 * wc + 16 * j + li, 4 + lk));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[i][j] = mfma_lp<__bf16>(ah[i], bh[j], acc[i][j]);
+                acc[i][j] = mfma_lp<__bf16>(ah[i], bl[j], acc[i][j]);
+                acc[i][j] = mfma_lp<__bf16>(al[i], bh[j], acc[i][j]);
+            }
+        if (c + 1 < n) lstore(buf ^ 1);
+        __syncthreads();
+    }
+}
+
 __device__ inline void split_bf16(double v, __bf16 &hi, __bf16 &lo) {
     hi = (__bf16)(float)v;
     lo = (__bf16)(float)(v - (double)(float)hi);
@@ -205,9 +278,12 @@ __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict
     int set, rest;
     if (!spinor_set_item(n_rt * n_ct, set, rest)) return;
     const int rt = rest / n_ct, ct = rest % n_ct;
-    const int koff = set ? 3 * nLp : 0, K = 3 * (set ? nSp : nLp), ld = 3 * (nLp + nSp);
+    // per set, Cb rows hold [hi | hi | lo] and Xb rows [hi | lo | hi]: A_hi, A_lo
+    // are blocks 0 and 2 of Cb, B_hi, B_lo blocks 0 and 1 of Xb
+    const int koff = set ? 3 * nLp : 0, blk = set ? nSp : nLp, ld = 3 * (nLp + nSp);
     f4v acc[4][4];
-    lp_gemm_tile<__bf16>(Cb + koff, ld, LBM * rt, 4 * nsp, Xb + koff, ld, LBM * ct, E, K, lds, acc);
+    lp_split_tile(Cb, ld, LBM * rt, 4 * nsp, koff, koff + 2 * blk, Xb, ld, LBM * ct, E, koff, koff + blk, blk, lds,
+                  acc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
 #pragma unroll
