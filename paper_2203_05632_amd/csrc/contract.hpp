@@ -3,6 +3,8 @@
 // green.hip for the definitions.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 // complex numbers in the contraction's arithmetic type F (FP64, or FP32 in
@@ -35,6 +37,49 @@ __device__ inline cx<F> conjc(cx<F> a) {
 template <typename F>
 __device__ inline cx<F> shfl_xor_c(cx<F> a, int mask) {
     return {__shfl_xor(a.re, mask, 64), __shfl_xor(a.im, mask, 64)};
+}
+
+// Lane moves within 16-lane rows by DPP (a VALU operand modifier, no LDS
+// traffic): CTRL 0x00-0xFF = quad_perm, 0x128 = row_ror:8, 0x141 =
+// row_half_mirror.
+template <int CTRL>
+__device__ inline float dpp(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp(double x) {
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)v, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL, typename F>
+__device__ inline cx<F> dpp_c(cx<F> a) {
+    return {dpp<CTRL>(a.re), dpp<CTRL>(a.im)};
+}
+// Sum over the 16 lanes of each row, the same bits in every lane: xor 8
+// (row_ror:8), then lane j <-> 7 - j within each half row (row_half_mirror),
+// xor 1, xor 2 -- each step adds a value and its partner's, so the two
+// lanes of a pair compute the same sum.
+template <typename F>
+__device__ inline cx<F> row16_sum(cx<F> v) {
+    v = cadd(v, dpp_c<0x128>(v));
+    v = cadd(v, dpp_c<0x141>(v));
+    v = cadd(v, dpp_c<0xB1>(v));
+    v = cadd(v, dpp_c<0x4E>(v));
+    return v;
+}
+// Lane l of each group of four consecutive lanes, in all four (quad_perm [l, l, l, l]).
+template <int L, typename F>
+__device__ inline cx<F> quad_bcast(cx<F> a) {
+    return dpp_c<0x55 * L>(a);
+}
+// The value of lane `l` (wave-uniform).
+__device__ inline double lane_value(double x, int l) {
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 template <typename F>
 __device__ inline cx<F> shfl_c(cx<F> a, int src) {
@@ -83,11 +128,9 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
         m2 = cadd(m2, cmulc(GB(Gm, 1, 1, k, b), GB(Gp, 1, 0, k, a)));  // [G-(2,4)^H G+(2,3)]_{ba}
     }
     cx<F> xt = cmul(m1, m2);
-    for (int mask = 8; mask >= 1; mask >>= 1) {
-        t1 = cadd(t1, shfl_xor_c(t1, mask));
-        t2 = cadd(t2, shfl_xor_c(t2, mask));
-        xt = cadd(xt, shfl_xor_c(xt, mask));
-    }
+    t1 = row16_sum(t1);
+    t2 = row16_sum(t2);
+    xt = row16_sum(xt);
     dir = exc = 0.0;
     if (ok) {
         const double W = hinv[p] * hinv[q] / wt;
@@ -114,14 +157,17 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
                 x23 = cadd(x23, cmul(GB(Gm, 1, 1, a, k), conjc(GB(Gp, 0, 1, b, k))));  // A24 P14^H
             }
             cx<F> s13 = {0, 0}, s24 = {0, 0}, s14 = {0, 0}, s23 = {0, 0};
-            const int row0 = lane & ~3;
-            for (int l = 0; l < 4; ++l) {
-                const int src = row0 | l;
-                s13 = cadd(s13, cmul(shfl_c(x13, src), GB(Gp, 1, 0, l, b)));  // (P14 A24^H) P23
-                s24 = cadd(s24, cmul(shfl_c(x24, src), GB(Gp, 0, 1, l, b)));  // (P23 A13^H) P14
-                s14 = cadd(s14, cmul(shfl_c(x14, src), GB(Gm, 1, 1, l, b)));  // (A13 P23^H) A24
-                s23 = cadd(s23, cmul(shfl_c(x23, src), GB(Gm, 0, 0, l, b)));  // (A24 P14^H) A13
-            }
+            auto gather = [&](auto lc) __attribute__((always_inline)) {  // element l of row a: lane 4 a + l
+                constexpr int l = decltype(lc)::value;
+                s13 = cadd(s13, cmul(quad_bcast<l>(x13), GB(Gp, 1, 0, l, b)));  // (P14 A24^H) P23
+                s24 = cadd(s24, cmul(quad_bcast<l>(x24), GB(Gp, 0, 1, l, b)));  // (P23 A13^H) P14
+                s14 = cadd(s14, cmul(quad_bcast<l>(x14), GB(Gm, 1, 1, l, b)));  // (A13 P23^H) A24
+                s23 = cadd(s23, cmul(quad_bcast<l>(x23), GB(Gm, 0, 0, l, b)));  // (A24 P14^H) A13
+            };
+            gather(std::integral_constant<int, 0>());
+            gather(std::integral_constant<int, 1>());
+            gather(std::integral_constant<int, 2>());
+            gather(std::integral_constant<int, 3>());
             const cx<F> p13 = GB(Gp, 0, 0, a, b), p24 = GB(Gp, 1, 1, a, b);
             const cx<F> a13 = GB(Gm, 0, 0, a, b), a24 = GB(Gm, 1, 1, a, b);
             const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
@@ -313,10 +359,10 @@ __device__ inline void contract_pairs(const cplx *Gm, const cplx *Gp, int PT, in
     contract_pair<GRAD, HT, F>(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m,
                                     hinv, wt, cgrad, R, dir, exc, Hm, Hp);
     // pairs of this wave summed in a fixed order (lanes 0, 16, 32, 48)
-    const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
-                 d3 = __shfl(dir, 48, 64);
-    const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
-                 x3 = __shfl(exc, 48, 64);
+    const double d0 = lane_value(dir, 0), d1 = lane_value(dir, 16), d2 = lane_value(dir, 32),
+                 d3 = lane_value(dir, 48);
+    const double x0 = lane_value(exc, 0), x1 = lane_value(exc, 16), x2 = lane_value(exc, 32),
+                 x3 = lane_value(exc, 48);
     if (lane == 0) {
         out[0] = ((d0 + d1) + d2) + d3;
         out[1] = ((x0 + x1) + x2) + x3;

@@ -401,10 +401,10 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
             double dir, exc;
             contract_pair<GRAD, uint32_t, float>(Gm + 8 * lk, Gp + 8 * lk, GLD, p, q, p < q && q < m, hinv, wt, cgrad,
                                                  R, dir, exc, Hm_t, Hp_t);
-            const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
-                         d3 = __shfl(dir, 48, 64);
-            const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
-                         x3 = __shfl(exc, 48, 64);
+            const double d0 = lane_value(dir, 0), d1 = lane_value(dir, 16), d2 = lane_value(dir, 32),
+                         d3 = lane_value(dir, 48);
+            const double x0 = lane_value(exc, 0), x1 = lane_value(exc, 16), x2 = lane_value(exc, 32),
+                         x3 = lane_value(exc, 48);
             dsum += ((d0 + d1) + d2) + d3;
             xsum += ((x0 + x1) + x2) + x3;
             __builtin_amdgcn_wave_barrier();
