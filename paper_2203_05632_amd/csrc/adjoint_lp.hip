@@ -52,7 +52,7 @@ template <int WN, int NCW>
 __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     const uint32_t *__restrict__ Hm, const uint32_t *__restrict__ Hp, const uint32_t *__restrict__ V,
     const float2 *__restrict__ psi, const double *__restrict__ tau, int n_tau, int R, int no, int nsp,
-    int n_occ_tiles, int n_col_tiles, int n_items, double2 *__restrict__ psibar, double *__restrict__ eps_part) {
+    int n_occ_tiles, int n_col_tiles, int n_items, float2 *__restrict__ psibar, double *__restrict__ eps_part) {
     constexpr int NTH = 128 * NCW, BN = NCW * WN, NJ = WN / 16;
     constexpr int NA = ABM * (AK / 4) / NTH;  // 16-byte A units per thread per chunk
     constexpr int NB = BN * (AK / 4) / NTH;   // 16-byte B units per thread per chunk
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
         for (int i = 0; i < 4; ++i) {
             const int xb = x0 + 64 * wr + 16 * i + 4 * lk;
             for (int v = 0; v < 4; ++v)
-                if (xb + v < R) psibar[(size_t)k * R + xb + v] = double2{pre[i][j][v], pim[i][j][v]};
+                if (xb + v < R) psibar[(size_t)k * R + xb + v] = float2{pre[i][j][v], pim[i][j][v]};
         }
     }
     if (tid < BN && k0 + tid < k_hi) eps_part[(size_t)rt * nsp + k0 + tid] = e_acc;
@@ -196,7 +196,7 @@ hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
     adj_lp_kernel<WN, NCW><<<8 * per, 128 * NCW, 0, c->stream>>>(
         reinterpret_cast<const uint32_t *>(c->Hm), reinterpret_cast<const uint32_t *>(c->Hp), c->Vt,
         reinterpret_cast<const float2 *>(c->psi), tau, n_tau, c->R, c->no, c->nsp, n_occ_tiles, n_col_tiles, n_items,
-        reinterpret_cast<double2 *>(c->psibar), c->eps_part);
+        reinterpret_cast<float2 *>(c->psibar), c->eps_part);  // FP32 accumulators as float2
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return prof_end(c, ps, MCMP2_K_ADJ_GEMM);

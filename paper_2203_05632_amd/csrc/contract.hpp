@@ -89,6 +89,10 @@ __device__ inline cx<F> shfl_c(cx<F> a, int src) {
 // Adjoint-block element stores: FP64 complex, or a BF16 pair packed in 32
 // bits (real part in the low half), rounded to nearest even.
 __device__ inline void h_store(double2 *H, size_t i, double re, double im) { H[i] = double2{re, im}; }
+__device__ inline uint32_t bf16_pair(float re, float im) {
+    const __bf16 r = (__bf16)re, m = (__bf16)im;
+    return (uint32_t)__builtin_bit_cast(unsigned short, r) | ((uint32_t)__builtin_bit_cast(unsigned short, m) << 16);
+}
 __device__ inline void h_store(uint32_t *H, size_t i, double re, double im) {
     const __bf16 r = (__bf16)(float)re, m = (__bf16)(float)im;
     H[i] = (uint32_t)__builtin_bit_cast(unsigned short, r) | ((uint32_t)__builtin_bit_cast(unsigned short, m) << 16);
@@ -173,9 +177,16 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
             const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
             // element (r, cc) = scale * v, its Hermitian partner (cc, r) = conj
             auto put = [&](HT *H, size_t r, size_t cc, cx<F> v, double scale) {
-                const double re = (double)v.re * scale, im = (double)v.im * scale;
-                h_store(H, r * R + cc, re, im);
-                h_store(H, cc * R + r, re, -im);
+                if constexpr (std::is_same_v<HT, uint32_t>) {
+                    // BF16 pairs: scaled in FP32 (BF16 keeps FP32's exponent range), rounded once
+                    const float sc = (float)scale, re = (float)v.re * sc, im = (float)v.im * sc;
+                    H[r * R + cc] = bf16_pair(re, im);
+                    H[cc * R + r] = bf16_pair(re, -im);
+                } else {
+                    const double re = (double)v.re * scale, im = (double)v.im * scale;
+                    h_store(H, r * R + cc, re, im);
+                    h_store(H, cc * R + r, re, -im);
+                }
             };
             put(Hm, r1, c3, csub(cmul(t2, p13), s13), cw);
             put(Hm, r2, c4, csub(cmul(t1, p24), s24), cw);
