@@ -75,9 +75,20 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
     const int r0 = 64 * blockIdx.x, k0 = 32 * blockIdx.y;
     const int t_lo = tpb * (int)blockIdx.z, t_hi = min(n_tau, t_lo + tpb);
     const int tid = threadIdx.x;
-    for (int e = tid; e < 32 * 64; e += 256) {  // coalesced along rows
-        const int kk = e >> 6, r = e & 63, k = k0 + kk;
-        tile[kk][r] = k < nsp ? psi[(size_t)k * R + r0 + r] : float2{0.f, 0.f};
+    {
+        // all eight loads in flight before the first LDS store (coalesced
+        // along rows; rows past nsp re-read the last spinor and store zero)
+        float2 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = tid + 256 * j, kk = e >> 6, r = e & 63;
+            v[j] = psi[(size_t)min(k0 + kk, nsp - 1) * R + r0 + r];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = tid + 256 * j, kk = e >> 6, r = e & 63;
+            tile[kk][r] = k0 + kk < nsp ? v[j] : float2{0.f, 0.f};
+        }
     }
     for (int t = t_lo; t < t_hi; ++t) {
         if (t > t_lo) __syncthreads();  // sq of the previous tau sample has been used

@@ -55,34 +55,37 @@ __device__ inline f4v mfma_lp(u32x4 a, u32x4 b, f4v c) {
 // dimensions lda / ldb in elements of T; rows at or past a_rows / b_rows read
 // the last valid row).  256 threads; wave (wr, wc) = (wave >> 1, wave & 1)
 // owns rows 64 wr .. and columns 64 wc ..; acc[i][j] element v is D[64 wr +
-// 16 i + 4 (l / 16) + v][64 wc + 16 j + l % 16].
+// 16 i + 4 (l / 16) + v][64 wc + 16 j + l % 16].  One LDS stage (32 KB): the
+// next chunk waits in registers while the current one is multiplied and is
+// stored after a barrier.
 template <typename T>
 __device__ __attribute__((always_inline)) inline void lp_gemm_tile(const T *__restrict__ A, int lda, int a_row0,
                                                                    int a_rows, const T *__restrict__ B, int ldb,
                                                                    int b_row0, int b_rows, int K, uint32_t *lds,
                                                                    f4v (&acc)[4][4]) {
-    constexpr int STAGE = 2 * LBM * LKW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
-    // staging unit u = tid + 256 j (j < 8): stage row u / 8 (A rows, then B rows), words 4 (u % 8) ..
-    const uint32_t *src[8];
+    // staging unit u = tid + 256 j (j < 8): stage row u / 8, words 4 (u % 8) ..; units j < 4
+    // are A rows, j >= 4 B rows (word offsets from A and B fit 32 bits)
+    const uint32_t *Aw = reinterpret_cast<const uint32_t *>(A), *Bw = reinterpret_cast<const uint32_t *>(B);
+    unsigned off[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int u = tid + 256 * j, row = u >> 3;
-        const T *p = row < LBM ? A + (size_t)min(a_row0 + row, a_rows - 1) * lda
-                               : B + (size_t)min(b_row0 + row - LBM, b_rows - 1) * ldb;
-        src[j] = reinterpret_cast<const uint32_t *>(p) + 4 * (u & 7);
+        off[j] = j < 4 ? (unsigned)min(a_row0 + row, a_rows - 1) * (unsigned)(lda / 2) + 4 * (u & 7)
+                       : (unsigned)min(b_row0 + row - LBM, b_rows - 1) * (unsigned)(ldb / 2) + 4 * (u & 7);
     }
     u32x4 rg[8];
     auto gload = [&](int w0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) rg[j] = *reinterpret_cast<const u32x4 *>(src[j] + w0);
+        for (int j = 0; j < 8; ++j)
+            rg[j] = *reinterpret_cast<const u32x4 *>((j < 4 ? Aw : Bw) + off[j] + w0);
     };
-    auto lstore = [&](int buf) __attribute__((always_inline)) {
+    auto lstore = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int u = tid + 256 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + 4 * swz(u >> 3, u & 7)]) = rg[j];
+            *reinterpret_cast<u32x4 *>(&lds[4 * swz(u >> 3, u & 7)]) = rg[j];
         }
     };
     for (int i = 0; i < 4; ++i)
@@ -90,26 +93,28 @@ __device__ __attribute__((always_inline)) inline void lp_gemm_tile(const T *__re
     const int n = K / (2 * LKW);
     if (n == 0) return;
     gload(0);
-    lstore(0);
+    lstore();
     __syncthreads();
     for (int c = 0; c < n; ++c) {
-        const int buf = c & 1;
         if (c + 1 < n) gload((c + 1) * LKW);
-        const uint32_t *l = &lds[buf * STAGE];
+        const uint32_t *l = lds;
 #pragma unroll
         for (int ks = 0; ks < LKW / 4; ks += 4) {  // 16-byte units: lane group lk reads unit ks + lk
-            u32x4 a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, ks + lk));
+            u32x4 b[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 b[j] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(LBM + 64 * wc + 16 * j + li, ks + lk));
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) {
+                const u32x4 a = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, ks + lk));
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_lp<T>(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_lp<T>(a, b[j], acc[i][j]);
+            }
         }
-        if (c + 1 < n) lstore(buf ^ 1);
+        if (c + 1 < n) {
+            __syncthreads();  // every wave is done with this chunk
+            lstore();
+        }
         __syncthreads();
     }
 }
@@ -303,15 +308,17 @@ __global__ __launch_bounds__(256) void spinor_lp_kernel(const __bf16 *__restrict
 }
 
 // grad_coeffs[s][mu][k] (double2): rows mu of one set (XTb), columns r = 4 k + 2 s + ri (PBb[set]).
-// The tile goes through LDS (rows of CGR floats: the 4-row steps of the
-// MFMA result layout fall in different banks) so that the stores run along
-// k: 32 consecutive complex values (512 B) per (s, mu).
+// The tile goes through LDS in two halves of 64 rows (rows of CGR floats: the
+// 4-row steps of the MFMA result layout fall in different banks) so that the
+// stores run along k: 32 consecutive complex values (512 B) per (s, mu).  With
+// one 32 KB main-loop stage and a 33 KB half tile, three blocks share a CU
+// (the register count, 156, allows three waves per SIMD; two blocks fit with a
+// full tile), so the epilogues' HBM traffic overlaps other blocks' main loops.
 constexpr int CGR = 132;
-__global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restrict__ XTb, const __bf16 *__restrict__ PBb,
-                                                           int nb, int nL, int nsp, int Ep, int n_rt_L, int n_rt_S,
-                                                           int n_ct, double *__restrict__ grad_coeffs,
-                                                           double *__restrict__ sum, double *__restrict__ comp) {
-    constexpr int MAIN = 2 * 2 * LBM * LKW, EPI = LBM * CGR;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void coef_grad_lp_kernel(
+    const __bf16 *__restrict__ XTb, const __bf16 *__restrict__ PBb, int nb, int nL, int nsp, int Ep, int n_rt_L,
+    int n_rt_S, int n_ct, double *__restrict__ grad_coeffs, double *__restrict__ sum, double *__restrict__ comp) {
+    constexpr int MAIN = 2 * LBM * LKW, EPI = (LBM / 2) * CGR;
     __shared__ __align__(16) uint32_t lds[MAIN > EPI ? MAIN : EPI];
     const int n_items = (n_rt_L + n_rt_S) * n_ct;
     const int item = xcd_item(n_items);
@@ -324,32 +331,66 @@ __global__ __launch_bounds__(256) void coef_grad_lp_kernel(const __bf16 *__restr
     lp_gemm_tile<__bf16>(XTb, Ep, mu0, mu_hi, PBb + (size_t)set * 4 * nsp * Ep, Ep, LBM * ct, 4 * nsp, Ep, lds, acc);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
-    __syncthreads();  // the main loop's last LDS reads are done
-    float *tile = reinterpret_cast<float *>(lds);  // [mu - mu0][r - LBM ct]
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) tile[(64 * wr + 16 * i + 4 * lk + v) * CGR + 64 * wc + 16 * j + li] = acc[i][j][v];
-    __syncthreads();
-    // complex value e = tid + 256 q: row e / 64 of the tile, spin s = (e / 32) % 2, k = k0 + e % 32
+    float *tile = reinterpret_cast<float *>(lds);  // [mu - mu0 - 64 h][r - LBM ct]
     const int k0 = (LBM * ct) / 4;
-    for (int q = 0; q < LBM * 64 / 256; ++q) {
-        const int e = tid + 256 * q, row = e >> 6, sp = (e >> 5) & 1, kk = e & 31;
-        const int mu = mu0 + row, k = k0 + kk;
-        if (mu >= mu_hi || k >= nsp) continue;
-        const float *src = tile + row * CGR + 4 * kk + 2 * sp;
-        const size_t o = (((size_t)sp * nb + mu) * nsp + k) * 2;
-        if (sum) {  // compensated accumulation instead of the store
-            double2 sv = *reinterpret_cast<const double2 *>(sum + o), cv = *reinterpret_cast<const double2 *>(comp + o);
-            neumaier(sv.x, cv.x, (double)src[0]);
-            neumaier(sv.y, cv.y, (double)src[1]);
-            *reinterpret_cast<double2 *>(sum + o) = sv;
-            *reinterpret_cast<double2 *>(comp + o) = cv;
-        } else {
-            *reinterpret_cast<double2 *>(grad_coeffs + o) = double2{(double)src[0], (double)src[1]};
+    // complex value e = tid + 256 q of a half: row e / 64, spin s = (e / 32) % 2, k = k0 + e % 32
+    constexpr int NQ = (LBM / 2) * 64 / 256;
+    constexpr int QB = 4;  // running sums loaded per batch before any is updated
+    for (int h = 0; h < 2; ++h) {
+        // the main loop's (or the previous half's) LDS reads are done: lp_gemm_tile
+        // ends with a barrier, and so does every half
+        if (wr == h) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        tile[(16 * i + 4 * lk + v) * CGR + 64 * wc + 16 * j + li] = acc[i][j][v];
         }
+        __syncthreads();
+        const int muh = mu0 + 64 * h;
+        if (!sum) {
+            for (int q = 0; q < NQ; ++q) {
+                const int e = tid + 256 * q, row = e >> 6, sp = (e >> 5) & 1, kk = e & 31;
+                const int mu = muh + row, k = k0 + kk;
+                if (mu >= mu_hi || k >= nsp) continue;
+                const float *src = tile + row * CGR + 4 * kk + 2 * sp;
+                *reinterpret_cast<double2 *>(grad_coeffs + (((size_t)sp * nb + mu) * nsp + k) * 2) =
+                    double2{(double)src[0], (double)src[1]};
+            }
+        } else {
+            // Compensated accumulation instead of the store.  The running sums
+            // of QB values are loaded before any of them is updated (values out
+            // of range load element 0 and are not written back); each element
+            // still takes one Neumaier step.
+#pragma unroll 1
+            for (int q0 = 0; q0 < NQ; q0 += QB) {
+                size_t o[QB];
+                bool ok[QB];
+                double2 sv[QB], cv[QB];
+#pragma unroll
+                for (int u = 0; u < QB; ++u) {
+                    const int e = tid + 256 * (q0 + u), row = e >> 6, sp = (e >> 5) & 1, kk = e & 31;
+                    const int mu = muh + row, k = k0 + kk;
+                    ok[u] = mu < mu_hi && k < nsp;
+                    o[u] = ok[u] ? (((size_t)sp * nb + mu) * nsp + k) * 2 : 0;
+                    sv[u] = *reinterpret_cast<const double2 *>(sum + o[u]);
+                    cv[u] = *reinterpret_cast<const double2 *>(comp + o[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < QB; ++u) {
+                    if (!ok[u]) continue;
+                    const int e = tid + 256 * (q0 + u), row = e >> 6, sp = (e >> 5) & 1, kk = e & 31;
+                    const float *src = tile + row * CGR + 4 * kk + 2 * sp;
+                    neumaier(sv[u].x, cv[u].x, (double)src[0]);
+                    neumaier(sv[u].y, cv[u].y, (double)src[1]);
+                    *reinterpret_cast<double2 *>(sum + o[u]) = sv[u];
+                    *reinterpret_cast<double2 *>(comp + o[u]) = cv[u];
+                }
+            }
+        }
+        __syncthreads();  // the half's LDS reads are done before the next half is written
     }
 }
 
@@ -407,6 +448,8 @@ hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, grad_out grad_coeffs) {
     const int n_rt_L = (c->nL + LBM - 1) / LBM, n_rt_S = (c->nS + LBM - 1) / LBM;
     const int n_ct = (4 * c->nsp + LBM - 1) / LBM;
     const int n_items = (n_rt_L + n_rt_S) * n_ct;
+    // lp_gemm_tile addresses its operand rows by 32-bit word offsets
+    if ((size_t)std::max(c->nb, 4 * c->nsp) * (size_t)(c->Ep / 2) >= ((size_t)1 << 32)) return hipErrorInvalidValue;
     coef_grad_lp_kernel<<<8 * ((n_items + 7) / 8), 256, 0, c->stream>>>(
         reinterpret_cast<const __bf16 *>(c->XTb), reinterpret_cast<const __bf16 *>(c->PBb), c->nb, c->nL, c->nsp,
         c->Ep, n_rt_L, n_rt_S, n_ct, grad_coeffs.out, grad_coeffs.sum, grad_coeffs.comp);
