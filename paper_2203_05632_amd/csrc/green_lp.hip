@@ -6,8 +6,10 @@
 // Operands.  For tau sample t, lp_operands writes
 //   U_t[row][K] = psi[k][row] * sqrt(s_t[k]),  K = 2 k (+1 for the imaginary part),
 // with s_t[k] = exp(+eps_k tau) (occupied) / exp(-eps_k tau) (virtual)
-// computed and square-rooted in FP64, the product rounded once to the
-// operand type.  The symmetric square-root scaling keeps both operands within
+// computed and square-rooted in FP64 and rounded to FP32; psi is FP32 (the
+// spinor GEMM's accumulators), so the product is formed in FP32 and rounded
+// once more to the operand type (hardware FP32 -> BF16 / FP16 conversions;
+// the double rounding changes a value by one operand unit in rare ties).  The symmetric square-root scaling keeps both operands within
 // the same range (FP16 included; terms below FP16's range flush to zero and
 // are weighted by exp(-eps tau) < 2^-24 relative to the largest).  Occupied
 // spinors fill K in [0, Ko), virtual ones [Ko, Ko + Kv), each padded with
@@ -41,20 +43,21 @@ constexpr int lrow() {
     return lkc<T>() + 16 / (int)sizeof(T);
 }
 
+// FP32 -> operand type, rounded to nearest even (v_cvt_pk_bf16_f32 / v_cvt_f16_f32)
 template <typename T>
-__device__ inline T to_op(double v);
+__device__ inline T to_op(float v);
 template <>
-__device__ inline __bf16 to_op<__bf16>(double v) {
+__device__ inline __bf16 to_op<__bf16>(float v) {
     return (__bf16)v;
 }
 template <>
-__device__ inline _Float16 to_op<_Float16>(double v) {
+__device__ inline _Float16 to_op<_Float16>(float v) {
     return (_Float16)v;
 }
 
 // (re, im) rounded to the operand type, packed into 32 bits (real part low)
 template <typename T>
-__device__ inline uint32_t pack_op(double re, double im) {
+__device__ inline uint32_t pack_op(float re, float im) {
     const T a = to_op<T>(re), b = to_op<T>(im);
     return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
 }
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
                                                           int Ko, int Ktot, int n_tau, int tpb, T *__restrict__ U,
                                                           uint32_t *__restrict__ V) {
     __shared__ float2 tile[32][65];
-    __shared__ double sq[32], sf[32];
+    __shared__ float sq[32], sf[32];  // sqrt(s_t[k]) and s_t[k], each rounded once from FP64
     const int r0 = 64 * blockIdx.x, k0 = 32 * blockIdx.y;
     const int t_lo = tpb * (int)blockIdx.z, t_hi = min(n_tau, t_lo + tpb);
     const int tid = threadIdx.x;
@@ -94,8 +97,9 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
         if (t > t_lo) __syncthreads();  // sq of the previous tau sample has been used
         if (tid < 32) {
             const int k = k0 + tid;
-            sf[tid] = k < nsp ? scale[(size_t)t * nsp + k] : 0.0;
-            sq[tid] = sqrt(sf[tid]);
+            const double sv = k < nsp ? scale[(size_t)t * nsp + k] : 0.0;
+            sf[tid] = (float)sv;
+            sq[tid] = (float)sqrt(sv);
         }
         __syncthreads();
         T *Ut = U + (size_t)t * R * Ktot;
@@ -104,8 +108,9 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
             if (k >= nsp) continue;
             const int K = k < no ? 2 * k : Ko + 2 * (k - no);
             const float2 v = tile[kk][r];
-            *reinterpret_cast<uint32_t *>(Ut + (size_t)(r0 + r) * Ktot + K) =
-                pack_op<T>((double)v.x * sq[kk], (double)v.y * sq[kk]);
+            // psi is FP32 (the spinor GEMM's accumulators): the products are
+            // formed in FP32 and rounded once more to the operand type
+            *reinterpret_cast<uint32_t *>(Ut + (size_t)(r0 + r) * Ktot + K) = pack_op<T>(v.x * sq[kk], v.y * sq[kk]);
         }
         if (V) {
             uint32_t *Vt = V + (size_t)t * nsp * R;
@@ -113,9 +118,7 @@ __global__ __launch_bounds__(256) void lp_operands_kernel(const float2 *__restri
                 const int kk = e >> 6, r = e & 63, k = k0 + kk;
                 if (k >= nsp) continue;
                 const float2 v = tile[kk][r];
-                const __bf16 re = (__bf16)(float)((double)v.x * sf[kk]), im = (__bf16)(float)((double)v.y * sf[kk]);
-                Vt[(size_t)k * R + r0 + r] = (uint32_t)__builtin_bit_cast(unsigned short, re) |
-                                             ((uint32_t)__builtin_bit_cast(unsigned short, im) << 16);
+                Vt[(size_t)k * R + r0 + r] = pack_op<__bf16>(v.x * sf[kk], v.y * sf[kk]);
             }
         }
     }

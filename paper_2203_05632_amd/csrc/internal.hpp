@@ -116,6 +116,18 @@ __device__ inline bool spinor_set_item(int n_pairs, int &set, int &pair) {
     return true;
 }
 
+// chi_mu(r) for the packed primitive record (A, zeta) + (N, lx | ly << 8 | lz << 16)
+__device__ inline double basis_value(const double4 &geo, const double2 &nl, double x, double y, double z) {
+    const double dx = x - geo.x, dy = y - geo.y, dz = z - geo.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const int l = (int)__double_as_longlong(nl.y);  // packed powers, bit pattern stored in a double
+    double poly = 1.0;
+    for (int i = 0; i < (l & 0xff); ++i) poly *= dx;
+    for (int i = 0; i < ((l >> 8) & 0xff); ++i) poly *= dy;
+    for (int i = 0; i < ((l >> 16) & 0xff); ++i) poly *= dz;
+    return nl.x * poly * exp(-geo.w * r2);
+}
+
 // g(r) of Eq. basisSet; gpar[I] = (c1 N(z1), z1, c2 N(z2), z2).
 __device__ inline double g_value(double x, double y, double z, const double *nuc, const double *gpar, int n_nuc) {
     double out = 0.0;
@@ -126,6 +138,36 @@ __device__ inline double g_value(double x, double y, double z, const double *nuc
         out = out + gpar[4 * I + 2] * exp(-gpar[4 * I + 3] * r2);
     }
     return out;
+}
+
+// Item i of the per-step scalars, i in [0, m + n_tau nsp + n_tau): for a walker
+// pair (i < m) the factor N_g / (g(r1) g(r2)) and the unit vector of r1 - r2;
+// then the tau scalings exp(+eps_k tau_t) (occupied k) / exp(-eps_k tau_t)
+// (virtual k); then the tau weights w(tau_t) = lambda exp(-lambda tau_t).
+__device__ inline void prep_scalar_item(int i, const double *walkers, int m, const double *nuc, const double *gpar,
+                                        int n_nuc, double Ng, double *hinv, double *rhat, const double *tau,
+                                        const double *eps, int n_tau, int nsp, int no, double lambda, double *scale,
+                                        double *wtau) {
+    if (i < m) {
+        const double *r = walkers + 6 * i;
+        const double g1 = g_value(r[0], r[1], r[2], nuc, gpar, n_nuc);
+        const double g2 = g_value(r[3], r[4], r[5], nuc, gpar, n_nuc);
+        hinv[i] = Ng / (g1 * g2);
+        const double dx = r[0] - r[3], dy = r[1] - r[4], dz = r[2] - r[5];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double inv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;  // coincident electrons: no direction
+        rhat[4 * i] = dx * inv;
+        rhat[4 * i + 1] = dy * inv;
+        rhat[4 * i + 2] = dz * inv;
+        rhat[4 * i + 3] = 0.0;
+    } else if (i < m + n_tau * nsp) {
+        const int j = i - m, t = j / nsp, k = j - t * nsp;
+        const double tv = tau[t];
+        scale[j] = k < no ? exp(eps[k] * tv) : exp(-eps[k] * tv);
+    } else {
+        const int t = i - m - n_tau * nsp;
+        wtau[t] = lambda * exp(-lambda * tau[t]);
+    }
 }
 
 // Event pair around a single kernel dispatch when kernel id `kid` is being
@@ -201,6 +243,9 @@ hipError_t launch_spinor_lp(const mcmp2_ctx *c);
 bool spinor_lp_tiled(const mcmp2_ctx *c);
 // XT -> XTb (gradients) and, with want_xb, the split-BF16 operand Xb
 hipError_t launch_x_lp(const mcmp2_ctx *c, bool want_xb);
+// step_prep for the tiled BF16 / FP16 spinor GEMM: the basis values go straight
+// to Xb (and XTb) without the FP64 XT, plus the per-step scalars
+hipError_t launch_step_prep_lp(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau);
 hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, grad_out grad_coeffs);
 // whether the BF16 coefficient gradient adds into running sums itself (enough tiles to hide its loads)
 bool coef_grad_lp_fused(const mcmp2_ctx *c);

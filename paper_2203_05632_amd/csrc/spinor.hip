@@ -23,18 +23,6 @@
 
 namespace {
 
-// chi_mu(r) for the packed primitive record (A, zeta) + (N, lx | ly << 8 | lz << 16)
-__device__ inline double basis_value(const double4 &geo, const double2 &nl, double x, double y, double z) {
-    const double dx = x - geo.x, dy = y - geo.y, dz = z - geo.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const int l = (int)__double_as_longlong(nl.y);  // packed powers, bit pattern stored in a double
-    double poly = 1.0;
-    for (int i = 0; i < (l & 0xff); ++i) poly *= dx;
-    for (int i = 0; i < ((l >> 8) & 0xff); ++i) poly *= dy;
-    for (int i = 0; i < ((l >> 16) & 0xff); ++i) poly *= dz;
-    return nl.x * poly * exp(-geo.w * r2);
-}
-
 // grid (ceil(n_pts / 128), nb + 1): rows y < nb evaluate basis function y at
 // every point; row y == nb runs a grid-stride loop over the walker factors,
 // the tau scalings and the tau weights.
@@ -54,28 +42,9 @@ __global__ __launch_bounds__(128) void step_prep_kernel(
         return;
     }
     const int n_items = m + n_tau * nsp + n_tau;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x) {
-        if (i < m) {
-            const double *r = walkers + 6 * i;
-            const double g1 = g_value(r[0], r[1], r[2], nuc, gpar, n_nuc);
-            const double g2 = g_value(r[3], r[4], r[5], nuc, gpar, n_nuc);
-            hinv[i] = Ng / (g1 * g2);
-            const double dx = r[0] - r[3], dy = r[1] - r[4], dz = r[2] - r[5];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double inv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;  // coincident electrons: no direction
-            rhat[4 * i] = dx * inv;
-            rhat[4 * i + 1] = dy * inv;
-            rhat[4 * i + 2] = dz * inv;
-            rhat[4 * i + 3] = 0.0;
-        } else if (i < m + n_tau * nsp) {
-            const int j = i - m, t = j / nsp, k = j - t * nsp;
-            const double tv = tau[t];
-            scale[j] = k < no ? exp(eps[k] * tv) : exp(-eps[k] * tv);
-        } else {
-            const int t = i - m - n_tau * nsp;
-            wtau[t] = lambda * exp(-lambda * tau[t]);
-        }
-    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x)
+        prep_scalar_item(i, walkers, m, nuc, gpar, n_nuc, Ng, hinv, rhat, tau, eps, n_tau, nsp, no, lambda, scale,
+                         wtau);
 }
 
 // Small problems (too few 16-spinor x 64-point tiles to fill the GPU):
@@ -354,6 +323,9 @@ hipError_t launch_spinor_typed(const mcmp2_ctx *c) {
 }  // namespace
 
 hipError_t launch_step_prep(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau) {
+    // the tiled BF16 / FP16 spinor GEMM reads only the BF16 basis values
+    if ((c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) && spinor_lp_tiled(c))
+        return launch_step_prep_lp(c, walkers, tau, n_tau);
     const int n_pts = 2 * c->m;
     dim3 grid((n_pts + 127) / 128, c->nb + 1);
     step_prep_kernel<<<grid, 128, 0, c->stream>>>(

@@ -254,6 +254,56 @@ __global__ __launch_bounds__(256) void x_lp_kernel(const double *__restrict__ XT
     }
 }
 
+// Basis values of the step straight into the BF16 operands (the tiled spinor
+// GEMM needs no FP64 copy): 32 (mu) x 32 (point) tiles, four values per
+// thread, XTb [mu][pt] written along points and Xb [pt][.] split as
+// [hi | lo | hi] along mu through an LDS transpose, as x_lp_kernel does from
+// XT; points in [n_pts, E) are the padding walkers, zero.  The last row of
+// blocks (blockIdx.y == ceil(E / 32)) computes the per-step scalars.
+// grid (ceil(nb / 32), ceil(E / 32) + 1).
+__global__ __launch_bounds__(256) void step_prep_lp_kernel(
+    const double *__restrict__ walkers, int n_pts, int E, int Ep, int nb, int nL, int nLp, int nSp,
+    const double4 *__restrict__ pgeo, const double2 *__restrict__ pnl, __bf16 *__restrict__ Xb,
+    __bf16 *__restrict__ XTb, int m, const double *__restrict__ nuc, const double *__restrict__ gpar, int n_nuc,
+    double Ng, double *__restrict__ hinv, double *__restrict__ rhat, const double *__restrict__ tau,
+    const double *__restrict__ eps, int n_tau, int nsp, int no, double lambda, double *__restrict__ scale,
+    double *__restrict__ wtau) {
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.y == (E + 31) / 32) {
+        const int i = blockIdx.x * 256 + tid;
+        if (i < m + n_tau * nsp + n_tau)
+            prep_scalar_item(i, walkers, m, nuc, gpar, n_nuc, Ng, hinv, rhat, tau, eps, n_tau, nsp, no, lambda,
+                             scale, wtau);
+        return;
+    }
+    __shared__ double tile[32][33];
+    const int mu0 = blockIdx.x * 32, pt0 = blockIdx.y * 32;
+    const int ldx = 3 * (nLp + nSp);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = tid + 256 * j, r = e >> 5, p = e & 31, mu = mu0 + r, pt = pt0 + p;
+        double v = 0.0;
+        if (mu < nb && pt < n_pts)
+            v = basis_value(pgeo[mu], pnl[mu], walkers[3 * pt], walkers[3 * pt + 1], walkers[3 * pt + 2]);
+        tile[r][p] = v;
+        if (XTb && mu < nb && pt < E) XTb[(size_t)mu * Ep + pt] = (__bf16)(float)v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = tid + 256 * j, p = e >> 5, r = e & 31, mu = mu0 + r, pt = pt0 + p;
+        if (mu < nb && pt < E) {
+            __bf16 hi, lo;
+            split_bf16(tile[r][p], hi, lo);
+            const int blk = mu < nL ? nLp : nSp;
+            __bf16 *o = Xb + (size_t)pt * ldx + split_base(mu, nL, nLp);
+            o[0] = hi;
+            o[blk] = lo;
+            o[2 * blk] = hi;
+        }
+    }
+}
+
 // psibar (float2 [nsp][R] in the BF16 / FP16 modes: the adjoint GEMM's FP32
 // accumulators; R index 4 pt + 2 set + s) -> PBb[set][4 k + 2 s + ri][pt]
 __global__ __launch_bounds__(256) void psibar_lp_kernel(const float2 *__restrict__ psibar, int nsp, int R, int E,
@@ -420,9 +470,20 @@ hipError_t launch_x_lp(const mcmp2_ctx *c, bool want_xb) {
     return hipGetLastError();
 }
 
+hipError_t launch_step_prep_lp(const mcmp2_ctx *c, const double *walkers, const double *tau, int n_tau) {
+    const int n_items = c->m + n_tau * c->nsp + n_tau;
+    const int bx = std::max((c->nb + 31) / 32, (n_items + 255) / 256);
+    dim3 g(bx, (c->E + 31) / 32 + 1);
+    step_prep_lp_kernel<<<g, 256, 0, c->stream>>>(
+        walkers, 2 * c->m, c->E, c->Ep, c->nb, c->nL, c->nLp, c->nbp - c->nLp,
+        reinterpret_cast<const double4 *>(c->pgeo), reinterpret_cast<const double2 *>(c->pnl),
+        reinterpret_cast<__bf16 *>(c->Xb), reinterpret_cast<__bf16 *>(c->XTb), c->m, c->nuc, c->gpar, c->n_nuc,
+        c->Ng, c->hinv, c->rhat, tau, c->eps, n_tau, c->nsp, c->no, c->lambda, c->scale, c->wtau);
+    return hipGetLastError();
+}
+
+// Xb (and XTb) were written by step_prep_lp_kernel in the same step.
 hipError_t launch_spinor_lp(const mcmp2_ctx *c) {
-    hipError_t e = launch_x_lp(c, true);
-    if (e != hipSuccess) return e;
     const int n_rt = (4 * c->nsp + LBM - 1) / LBM, n_ct = (c->E + LBM - 1) / LBM;
     spinor_lp_kernel<<<16 * ((n_rt * n_ct + 7) / 8), 256, 0, c->stream>>>(
         reinterpret_cast<const __bf16 *>(c->Cb), reinterpret_cast<const __bf16 *>(c->Xb), c->nsp, c->nLp,
