@@ -52,7 +52,8 @@ template <int WN, int NCW>
 __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     const uint32_t *__restrict__ Hm, const uint32_t *__restrict__ Hp, const uint32_t *__restrict__ V,
     const float2 *__restrict__ psi, const double *__restrict__ tau, int n_tau, int R, int no, int nsp,
-    int n_occ_tiles, int n_col_tiles, int n_items, float2 *__restrict__ psibar, double *__restrict__ eps_part) {
+    int n_occ_tiles, int n_col_tiles, int n_items, int Ep, unsigned short *__restrict__ PBb,
+    double *__restrict__ eps_part) {
     constexpr int NTH = 128 * NCW, BN = NCW * WN, NJ = WN / 16;
     constexpr int NA = ABM * (AK / 4) / NTH;  // 16-byte A units per thread per chunk
     constexpr int NB = BN * (AK / 4) / NTH;   // 16-byte B units per thread per chunk
@@ -172,14 +173,37 @@ __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
         __syncthreads();
     }
 
-    for (int j = 0; j < NJ; ++j) {
-        const int k = k0 + WN * wc + 16 * j + li;
-        if (k >= k_hi) continue;
-        for (int i = 0; i < 4; ++i) {
-            const int xb = x0 + 64 * wr + 16 * i + 4 * lk;
-            for (int v = 0; v < 4; ++v)
-                if (xb + v < R) psibar[(size_t)k * R + xb + v] = float2{pre[i][j][v], pim[i][j][v]};
+    // Psibar tile -> the coefficient gradient's BF16 operand PBb[set][4 k + 2 s + ri][pt]
+    // (points contiguous; row x = 4 pt + 2 set + s), one wave column (WN spinors) at a
+    // time through LDS: stg[kk][2 set + s][ri][32 points], spinor rows padded to 528 bytes
+    // (16-byte aligned reads; the 16 spinors a wave writes fall in distinct banks).
+    constexpr int SR = 264;  // bf16 per staged spinor
+    unsigned short *stg = reinterpret_cast<unsigned short *>(&lds[0][0]);
+    const int pt0 = x0 / 4, n_pt = min(32, (R - x0) / 4);  // R - x0 is a multiple of 64
+    const size_t plane = (size_t)4 * nsp * Ep;
+    for (int g = 0; g < NCW; ++g) {
+        if (wc == g) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        unsigned short *o = stg + (16 * j + li) * SR + 2 * v * 32 + 16 * wr + 4 * i + lk;
+                        o[0] = __builtin_bit_cast(unsigned short, (__bf16)pre[i][j][v]);
+                        o[32] = __builtin_bit_cast(unsigned short, (__bf16)pim[i][j][v]);
+                    }
         }
+        __syncthreads();
+        for (int e = tid; e < WN * 8 * 4; e += NTH) {  // spinor kk, staged row (2 set + s) * 2 + ri, 8 points
+            const int kk = e >> 5, row = (e >> 2) & 7, unit = e & 3;
+            const int k = k0 + WN * g + kk;
+            if (k >= k_hi || 8 * unit >= n_pt) continue;
+            const int set = row >> 2, sri = row & 3;  // sri = 2 s + ri
+            *reinterpret_cast<u32x4 *>(PBb + set * plane + (size_t)(4 * k + sri) * Ep + pt0 + 8 * unit) =
+                *reinterpret_cast<const u32x4 *>(stg + kk * SR + row * 32 + 8 * unit);
+        }
+        __syncthreads();  // the staging is rewritten for the next wave column
     }
     if (tid < BN && k0 + tid < k_hi) eps_part[(size_t)rt * nsp + k0 + tid] = e_acc;
 }
@@ -196,7 +220,7 @@ hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
     adj_lp_kernel<WN, NCW><<<8 * per, 128 * NCW, 0, c->stream>>>(
         reinterpret_cast<const uint32_t *>(c->Hm), reinterpret_cast<const uint32_t *>(c->Hp), c->Vt,
         reinterpret_cast<const float2 *>(c->psi), tau, n_tau, c->R, c->no, c->nsp, n_occ_tiles, n_col_tiles, n_items,
-        reinterpret_cast<float2 *>(c->psibar), c->eps_part);  // FP32 accumulators as float2
+        c->Ep, reinterpret_cast<unsigned short *>(c->PBb), c->eps_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return prof_end(c, ps, MCMP2_K_ADJ_GEMM);

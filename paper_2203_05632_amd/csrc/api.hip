@@ -322,7 +322,7 @@ extern "C" int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const 
         c->Hm = reinterpret_cast<double *>(hm);
         TRY(dalloc(&hp, hbytes));
         c->Hp = reinterpret_cast<double *>(hp);
-        TRY(dalloc(&c->psibar, 2 * (size_t)nsp * c->R));
+        if (!h16) TRY(dalloc(&c->psibar, 2 * (size_t)nsp * c->R));  // the 16-bit modes write PBb instead
         TRY(dalloc(&c->eps_part, (size_t)(c->R / 32) * nsp));
         if (h16) TRY(dalloc(&c->Vt, (size_t)n_tau_max * nsp * c->R));
         if (h16 && !coef_grad_lp_fused(c)) TRY(dalloc(&c->gstage, (size_t)((nsp + 1) & ~1) + 4 * (size_t)nb * nsp));

@@ -68,7 +68,7 @@ struct mcmp2_ctx {
     // packed BF16 pairs, real part in the low half (BF16, FP16 modes)
     double *Hm = nullptr;       // adjoint of G-
     double *Hp = nullptr;       // adjoint of G+
-    double *psibar = nullptr;   // [nsp][R] complex gradient of psi
+    double *psibar = nullptr;   // [nsp][R] complex gradient of psi (FP64, FP32 modes)
     uint32_t *Vt = nullptr;     // BF16 / FP16 modes: [n_tau_max][nsp][R] psi s_t as packed BF16 pairs
     // BF16 / FP16 modes: BF16 operands of the spinor GEMM and the coefficient
     // gradient (primitive sets padded to nLp, nSp = nbp - nLp; points padded
@@ -77,7 +77,7 @@ struct mcmp2_ctx {
     void *Cb = nullptr;   // [4 nsp][3 nbp]: row 4 k + 2 s + ri = part ri of C[s][mu][k], split [hi|hi|lo] per set
     void *Xb = nullptr;   // [E][3 nbp] basis values per point, split [hi|lo|hi] per set
     void *XTb = nullptr;  // [nb][Ep] basis values per primitive (gradients)
-    void *PBb = nullptr;  // [2 sets][4 nsp][Ep] psi gradient (gradients)
+    void *PBb = nullptr;  // [2 sets][4 nsp][Ep] psi gradient (gradients), written by the adjoint GEMM
     double *eps_part = nullptr; // [row tiles][nsp] eps-gradient partials (32-row tiles, or 128-row in BF16 / FP16 modes)
     // BF16 / FP16 modes below one coefficient-gradient tile per two CUs: staging
     // of both gradients for mcmp2_step_accumulate ([nsp] rounded up to even,

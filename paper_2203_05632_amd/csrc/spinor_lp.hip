@@ -304,22 +304,6 @@ __global__ __launch_bounds__(256) void step_prep_lp_kernel(
     }
 }
 
-// psibar (float2 [nsp][R] in the BF16 / FP16 modes: the adjoint GEMM's FP32
-// accumulators; R index 4 pt + 2 set + s) -> PBb[set][4 k + 2 s + ri][pt]
-__global__ __launch_bounds__(256) void psibar_lp_kernel(const float2 *__restrict__ psibar, int nsp, int R, int E,
-                                                        int Ep, __bf16 *__restrict__ PBb) {
-    const int pt = blockIdx.x * 256 + threadIdx.x, k = blockIdx.y;
-    if (pt >= E) return;
-    const size_t plane = (size_t)4 * nsp * Ep;
-    for (int c = 0; c < 4; ++c) {
-        const float2 v = psibar[(size_t)k * R + 4 * pt + c];
-        const int set = c >> 1, s = c & 1;
-        __bf16 *o = PBb + set * plane + (size_t)(4 * k + 2 * s) * Ep + pt;
-        o[0] = (__bf16)(float)v.x;
-        o[Ep] = (__bf16)(float)v.y;
-    }
-}
-
 // Work items dealt to the XCDs in contiguous ranges (block b runs on XCD b % 8).
 __device__ inline int xcd_item(int n_items) {
     const int per = (n_items + 7) / 8;
@@ -500,12 +484,9 @@ bool coef_grad_lp_fused(const mcmp2_ctx *c) {
     return (n_rt_L + n_rt_S) * n_ct >= 2 * c->n_cu;
 }
 
+// PBb (the psi gradient as BF16, points contiguous) was written by the
+// adjoint GEMM of the same step (adjoint_lp.hip).
 hipError_t launch_coef_grad_lp(const mcmp2_ctx *c, grad_out grad_coeffs) {
-    dim3 g1((c->E + 255) / 256, c->nsp);
-    psibar_lp_kernel<<<g1, 256, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->psibar), c->nsp, c->R, c->E,
-                                                c->Ep, reinterpret_cast<__bf16 *>(c->PBb));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const int n_rt_L = (c->nL + LBM - 1) / LBM, n_rt_S = (c->nS + LBM - 1) / LBM;
     const int n_ct = (4 * c->nsp + LBM - 1) / LBM;
     const int n_items = (n_rt_L + n_rt_S) * n_ct;
