@@ -177,11 +177,12 @@ int mcmp2_set_coefficients(mcmp2_ctx *ctx, const double *coeffs, const double *e
  * on, weighted per walker pair by the 4x4 coefficients of g in the basis
  * (1, alpha_x, alpha_y, alpha_z) x (1, alpha_x, alpha_y, alpha_z).
  * The step's outputs keep their meaning (direct, exchange, total of the
- * estimator).  The Gaunt and Breit terms are evaluated in the FP64 and FP32
- * modes (the contraction in FP64 in both) and without gradient outputs.
- * Errors: EINVAL (null context, unknown kind, Gaunt / Breit in the BF16 /
- * FP16 modes).  mcmp2_step returns EINVAL when gradient outputs are requested with
- * a non-Coulomb interaction.
+ * estimator).  The Gaunt and Breit terms are evaluated in every precision
+ * mode, the alpha-weighted contraction in FP64 on the mode's Green's
+ * functions (in the BF16 / FP16 modes through the 32 x 32-tile Green's
+ * kernel at every size), and without gradient outputs.
+ * Errors: EINVAL (null context, unknown kind).  mcmp2_step returns EINVAL when
+ * gradient outputs are requested with a non-Coulomb interaction.
  */
 int mcmp2_set_interaction(mcmp2_ctx *ctx, int32_t interaction);
 

@@ -161,7 +161,7 @@ class Context:
 
     def set_interaction(self, kind: str) -> None:
         """Electron-electron interaction of the following steps: "coulomb"
-        (default), "gaunt" or "breit" (FP64 and FP32 contexts, no gradients)."""
+        (default), "gaunt" or "breit" (any precision, no gradients)."""
         check(self._lib.mcmp2_set_interaction(self._h, INTERACTIONS[kind]))
 
     def pair_weights(self, walkers: torch.Tensor, w: torch.Tensor) -> torch.Tensor:

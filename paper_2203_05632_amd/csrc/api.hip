@@ -445,10 +445,6 @@ extern "C" int mcmp2_set_interaction(mcmp2_ctx *c, int32_t interaction) {
         set_error("interaction %d is not one of MCMP2_COULOMB, _GAUNT, _BREIT", interaction);
         return MCMP2_EINVAL;
     }
-    if (interaction != MCMP2_COULOMB && c->precision != MCMP2_FP64 && c->precision != MCMP2_FP32) {
-        set_error("the Gaunt and Breit terms are available in the FP64 and FP32 modes only");
-        return MCMP2_EINVAL;
-    }
     c->interaction = interaction;
     return MCMP2_OK;
 }

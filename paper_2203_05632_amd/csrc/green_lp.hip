@@ -219,14 +219,20 @@ __device__ __attribute__((always_inline)) inline void lp_stream(const T *__restr
 }
 
 // HT: element type of the adjoint blocks (FP64 complex with FP32 operands,
-// packed BF16 pairs with BF16 / FP16 operands).
-template <typename T, int NT, bool GRAD, typename HT>
+// packed BF16 pairs with BF16 / FP16 operands).  BREIT: the Gaunt / Breit
+// interaction (one tau per block, no gradients): the FP32 Green's functions
+// are staged in FP64 and go through the FP64 alpha-weighted contraction of
+// the FP64 / FP32 modes (contract_pairs_breit; rhat [m_pad][4] unit vectors of
+// r1p - r2p, gauge = weight of the second Breit term).
+template <typename T, int NT, bool GRAD, typename HT, bool BREIT = false>
 __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, int Ko, int Ktot,
                                                        const double *__restrict__ wtau, const double *__restrict__ hinv,
                                                        const int *__restrict__ tiles, const int *__restrict__ work,
                                                        int n_slots, int R, int m, int t_base,
                                                        double *__restrict__ partial, HT *__restrict__ Hm,
-                                                       HT *__restrict__ Hp, double cgrad) {
+                                                       HT *__restrict__ Hp, double cgrad,
+                                                       const double *__restrict__ rhat = nullptr, double gauge = 0.0) {
+    static_assert(!BREIT || (NT == 1 && !GRAD), "the Gaunt / Breit contraction takes one tau and no gradients");
     const int t0 = t_base + (int)blockIdx.y * NT;  // tau samples t0 .. t0 + NT - 1
     constexpr int PANEL_BYTES = 2 * NT * 2 * 32 * lrow<T>() * (int)sizeof(T);
     constexpr int EPI_BYTES = 4 * 512 * (int)sizeof(cplx);
@@ -263,11 +269,14 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
         // wave-private staging (the K loop ended with a block barrier); one
         // wave's LDS accesses complete in order
         __builtin_amdgcn_wave_barrier();
-        // FP32 contraction arithmetic (weights and sums in FP64)
-        contract_pairs<GRAD, HT, float>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
-                                        partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
-                                        GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
-                                        GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
+        if constexpr (BREIT)
+            contract_pairs_breit(Gm, Gp, PT, QT, m, hinv, rhat, gauge, wtau[t0 + t],
+                                 partial + ((size_t)(t0 + t) * n_slots + slot) * 2);
+        else  // FP32 contraction arithmetic (weights and sums in FP64)
+            contract_pairs<GRAD, HT, float>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
+                                            partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
+                                            GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
+                                            GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -467,6 +476,15 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     uint32_t *Hm = reinterpret_cast<uint32_t *>(c->Hm), *Hp = reinterpret_cast<uint32_t *>(c->Hp);
     const int nblocks = c->n_slots / 4;
+    if (c->interaction != MCMP2_COULOMB) {  // mcmp2_step rejects gradients with it
+        const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
+        const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
+        green_lp_kernel<T, 1, false, uint32_t, true><<<dim3(nblocks, n_tau), 256, 0, c->stream>>>(
+            U, c->Ko, c->Ktot, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->m, 0, c->partial, nullptr,
+            nullptr, 0.0, c->rhat, gauge);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return prof_end(c, ps, MCMP2_K_GREEN_GEMM);
+    }
     constexpr int NTMAX = 4;
     for (int t0 = 0; t0 < n_tau; t0 += NTMAX) {
         const int nt = std::min(NTMAX, n_tau - t0);
@@ -496,8 +514,12 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
 
 }  // namespace
 
+// The 128 x 128-tile kernel for the Coulomb interaction once it has 256 work
+// items; the Gaunt / Breit interaction always takes the 32 x 32-tile kernel,
+// whose epilogue layout the alpha-weighted contraction reads.
 bool green_big_selected(const mcmp2_ctx *c, int n_tau) {
-    return (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) && c->n_tp16 * n_tau >= 256;
+    return (c->precision == MCMP2_BF16 || c->precision == MCMP2_FP16) && c->interaction == MCMP2_COULOMB &&
+           c->n_tp16 * n_tau >= 256;
 }
 
 void build_big_tiles(int T16, std::vector<int> &tiles) {

@@ -4,7 +4,8 @@ the HIP path through the C ABI against the FP64 oracle's trace form with
 Dirac-matrix insertions, on identical seeded walkers and tau samples.
 
 Tolerance as for the Coulomb path: 1e-10 relative per tau and part, on the
-scale max(|value|, mean |pair term|).
+scale max(|value|, mean |pair term|) in FP64 mode; FP32, BF16 and FP16 modes
+within their regression guards (below).
 """
 import numpy as np
 import pytest
@@ -101,12 +102,48 @@ def test_breit_step_is_bitwise_deterministic():
     assert np.array_equal(a, b)
 
 
-def test_breit_rejected_in_bf16_fp16_and_with_gradients():
+# BF16 / FP16 Green's functions, regression guards on the pair scale, set as
+# for the Coulomb steps (three times the largest deviation measured over these
+# cases): BF16 9.6e-4 measured, the Coulomb guard 1e-2 kept; FP16 4.8e-4
+# measured (ragged C0, tau = 0.2; the Coulomb FP16 steps stay below 1.6e-4)
+# -> 1.5e-3.  The Gaunt / Breit terms couple the large and the small (kappa_S
+# scaled) components, whose FP16 operands keep fewer significant bits at the
+# bottom of FP16's range.
+LP_BOUND = {"bf16": 1e-2, "fp16": 1.5e-3}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("kind", ["gaunt", "breit"])
+@pytest.mark.parametrize("name,over,taus", [("C0", dict(m=13, n_occ=6, n_vir=10), [0.2, 1.3]),
+                                            ("C1", {}, [0.17, 0.83])])
+def test_breit_low_precision_near_oracle(prec, kind, name, over, taus):
+    """BF16 / FP16 mode: the mode's Green's functions (32 x 32 tiles) through
+    the FP64 alpha-weighted contraction, against the FP64 oracle within the
+    mode's step guard; the alpha terms are resolved above that error (the
+    oracle's Breit value differs from its Coulomb value by more than twice
+    the error)."""
+    inp = make_inputs(name, n_tau=len(taus), **over)
+    wk = initial_walkers(inp)
+    ctx = _ctx(inp, precision=prec, n_tau_max=len(taus))
+    ctx.set_interaction(kind)
+    got = _gpu_step(ctx, wk, np.array(taus))
+    lam, Ng = tau_lambda(inp.eps, inp.n_occ), n_g(inp.nuc_xyz, inp.wfn)
+    res, pairs = oi.step_estimate(inp, wk, taus, lam, Ng, return_pairs=True, interaction=kind)
+    ref = res.numpy()
+    coul = oi.step_estimate(inp, wk, taus, lam, Ng).numpy()
+    for t in range(len(taus)):
+        scale = float(pairs[t].real.abs().mean())
+        err = rel_err(got[t], ref[t], norm=scale)
+        alpha = float(np.max(np.abs(ref[t] - coul[t]))) / scale
+        print(f"{prec} {kind} {name} {over} tau={taus[t]}: error / scale = {err:.3e}, "
+              f"(Breit - Coulomb) / scale = {alpha:.3e}", flush=True)
+        assert err < LP_BOUND[prec]
+        assert alpha > 2 * err
+
+
+def test_breit_rejected_with_gradients():
     from paper_2203_05632_amd._lib import MCMP2Error
     inp = make_inputs("C0")
-    for prec in ("bf16", "fp16"):
-        with pytest.raises(MCMP2Error, match="FP64"):
-            _ctx(inp, precision=prec).set_interaction("breit")
     ctx = _ctx(inp, want_grad=True)
     ctx.set_interaction("gaunt")
     wk = dev(initial_walkers(inp))
