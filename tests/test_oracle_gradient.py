@@ -66,3 +66,52 @@ def test_gradient_invariants(grad_case):
     assert abs(vir - 4 * val) <= 1e-10 * abs(val)
     phase = np.sum(inp.coeffs.conj() * gc, axis=(0, 1)).imag
     assert np.abs(phase).max() <= 1e-10 * np.abs(gc).max()
+
+
+@pytest.fixture(scope="module")
+def breit_grad_case():
+    inp = make_inputs("C0", n_tau=2)
+    wk = initial_walkers(inp)
+    Ng = n_g(inp.nuc_xyz, inp.wfn)
+    lam = tau_lambda(inp.eps, inp.n_occ)
+    taus = np.array([0.3, 1.1])
+    parts, val, ge, gc = step_value_and_grad(inp, wk, taus, lam, Ng, interaction="breit")
+    return inp, wk, Ng, lam, taus, val, ge, gc
+
+
+def test_breit_gradient_finite_differences_and_invariants(breit_grad_case):
+    """The same pins for the gradient through the Breit forward (Sec. II, the
+    full interaction operator): central differences of the oracle's Breit
+    step along eps and coefficient probes, the eps-shift invariance, Euler's
+    degree-4 relations and the phase invariance (the alpha matrices act on
+    the components, not on the orbitals, so all of them still hold), and the
+    gradient differs from the Coulomb one."""
+    inp, wk, Ng, lam, taus, val, ge, gc = breit_grad_case
+    h = 1e-5
+    rng = probe_rng(2)
+    for k in rng.choice(inp.n_sp, size=6, replace=False):
+        ep, em = inp.eps.copy(), inp.eps.copy()
+        ep[k] += h
+        em[k] -= h
+        fd = (step_value(inp, wk, taus, lam, Ng, eps=ep, interaction="breit")
+              - step_value(inp, wk, taus, lam, Ng, eps=em, interaction="breit")) / (2 * h)
+        assert abs(fd - ge[k]) <= 1e-6 * np.abs(ge).max()
+    for _ in range(6):
+        s, mu, k = rng.integers(2), rng.integers(inp.n_b), rng.integers(inp.n_sp)
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            Cp, Cm = inp.coeffs.copy(), inp.coeffs.copy()
+            Cp[s, mu, k] += unit * h
+            Cm[s, mu, k] -= unit * h
+            fd = (step_value(inp, wk, taus, lam, Ng, coeffs=Cp, interaction="breit")
+                  - step_value(inp, wk, taus, lam, Ng, coeffs=Cm, interaction="breit")) / (2 * h)
+            an = gc[s, mu, k].real if part == "re" else gc[s, mu, k].imag
+            assert abs(fd - an) <= 1e-6 * np.abs(gc).max()
+    assert abs(ge.sum()) <= 1e-12 * np.abs(ge).max() * inp.n_sp
+    no = inp.n_occ
+    occ = np.sum((inp.coeffs.conj() * gc)[:, :, :no]).real
+    vir = np.sum((inp.coeffs.conj() * gc)[:, :, no:]).real
+    assert abs(occ - 4 * val) <= 1e-10 * abs(val)
+    assert abs(vir - 4 * val) <= 1e-10 * abs(val)
+    assert np.abs(np.sum(inp.coeffs.conj() * gc, axis=(0, 1)).imag).max() <= 1e-10 * np.abs(gc).max()
+    _, _, ge_c, gc_c = step_value_and_grad(inp, wk, taus, lam, Ng)
+    assert np.abs(gc - gc_c).max() > 1e-4 * np.abs(gc).max()
