@@ -127,7 +127,7 @@ int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps
  *   (ESTATE otherwise); they come from a hand-written adjoint of the same
  *   step (Green's-function blocks recomputed, not stored between calls).
  * Errors: EINVAL (null pointers, n_tau out of range, gradient outputs with a
- * non-Coulomb interaction), ESTATE, EDEVICE.
+ * non-Coulomb interaction in the BF16 / FP16 modes), ESTATE, EDEVICE.
  */
 int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
                double *value, double *grad_eps, double *grad_coeffs);
@@ -147,7 +147,8 @@ int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t
  * The caller zeroes the pairs to start; the running total of a gradient is
  * sum + comp.
  * Errors: EINVAL (null pointers, n_tau out of range, a non-Coulomb
- * interaction), ESTATE (context without want_grad), EDEVICE.
+ * interaction in the BF16 / FP16 modes), ESTATE (context without want_grad),
+ * EDEVICE.
  */
 int mcmp2_step_accumulate(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
                           double *eps_sum, double *eps_comp, double *coeffs_sum, double *coeffs_comp);
@@ -180,9 +181,13 @@ int mcmp2_set_coefficients(mcmp2_ctx *ctx, const double *coeffs, const double *e
  * estimator).  The Gaunt and Breit terms are evaluated in every precision
  * mode, the alpha-weighted contraction in FP64 on the mode's Green's
  * functions (in the BF16 / FP16 modes through the 32 x 32-tile Green's
- * kernel at every size), and without gradient outputs.
- * Errors: EINVAL (null context, unknown kind).  mcmp2_step returns EINVAL when
- * gradient outputs are requested with a non-Coulomb interaction.
+ * kernel at every size).  Gradient outputs are available with them in the
+ * FP64 and FP32 modes: the adjoint of the alpha-weighted contraction is
+ * formed in FP64 beside it, and the adjoint GEMMs are those of the Coulomb
+ * interaction.
+ * Errors: EINVAL (null context, unknown kind).  mcmp2_step and
+ * mcmp2_step_accumulate return EINVAL when gradient outputs are requested
+ * with a non-Coulomb interaction in the BF16 / FP16 modes.
  */
 int mcmp2_set_interaction(mcmp2_ctx *ctx, int32_t interaction);
 

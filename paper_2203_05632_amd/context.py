@@ -161,7 +161,8 @@ class Context:
 
     def set_interaction(self, kind: str) -> None:
         """Electron-electron interaction of the following steps: "coulomb"
-        (default), "gaunt" or "breit" (any precision, no gradients)."""
+        (default), "gaunt" or "breit" (any precision; gradients in the FP64 and
+        FP32 modes)."""
         check(self._lib.mcmp2_set_interaction(self._h, INTERACTIONS[kind]))
 
     def pair_weights(self, walkers: torch.Tensor, w: torch.Tensor) -> torch.Tensor:

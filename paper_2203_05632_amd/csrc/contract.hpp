@@ -228,19 +228,80 @@ __device__ __forceinline__ double bw(int mu, int nu, double ux, double uy, doubl
     return -0.5 * ((mu == nu ? 1.0 : 0.0) + c * um * un);
 }
 
+// Exchange blocks of the Breit adjoint.  Each has the form
+//   Y = sum_{al, be} s_al L K[al][be] Rm s_be,
+//   K[al][be] = sum_{ga, de} B12[al][ga] B34[be][de] s_de M s_ga
+// (L, M, Rm: 4x4 blocks read through accessors).  Lane (al, be) = (l16 >> 2,
+// l16 & 3) of the pair's group builds its K (s_de M s_ga: M read at permuted
+// indices with phases) and the product (s_al L) K (Rm s_be), the outer
+// alpha factors folded into row / column reads of L and Rm, so every register
+// index is a compile-time one; the 16 entries are then summed over the group
+// (row16_sum) and lane (a, b) = (l16 >> 2, l16 & 3) keeps entry [a][b].
+template <typename FL, typename FM, typename FR>
+__device__ inline cplx breit_xblock(FL L, FM M, FR Rm, int l16, double ux, double uy, double uz, double vx, double vy,
+                                    double vz, double c) {
+    const int al = l16 >> 2, be = l16 & 3, xa = sx(al), xb = sx(be);
+    cplx K[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) K[k][l] = {0, 0};
+#pragma unroll
+    for (int ga = 0; ga < 4; ++ga)
+#pragma unroll
+        for (int de = 0; de < 4; ++de) {
+            const double w = bw(al, ga, ux, uy, uz, c) * bw(be, de, vx, vy, vz, c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    // (s_de M s_ga)[k][l] = ph(de, k) M[k ^ x_de][l ^ x_ga] ph(ga, l ^ x_ga)
+                    const cplx z = sph(de, k, sph(ga, l ^ sx(ga), M(k ^ sx(de), l ^ sx(ga))));
+                    K[k][l] = {K[k][l].re + w * z.re, K[k][l].im + w * z.im};
+                }
+        }
+    cplx LK[4][4];  // (s_al L)[i][k] = ph(al, i) L[i ^ x_al][k]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            cplx z = {0, 0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) z = cadd(z, cmul(L(i ^ xa, k), K[k][l]));
+            LK[i][l] = sph(al, i, z);
+        }
+    cplx mine = {0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // (Rm s_be)[l][j] = Rm[l][j ^ x_be] ph(be, j ^ x_be)
+            cplx z = {0, 0};
+#pragma unroll
+            for (int l = 0; l < 4; ++l) z = cadd(z, cmul(LK[i][l], Rm(l, j ^ xb)));
+            z = row16_sum(sph(be, j ^ xb, z));
+            if (4 * i + j == l16) mine = z;
+        }
+    return mine;
+}
+
 // One walker pair (p, q) per 16 lanes, tiles as for contract_pair (FP64
 // complex); rhat [m_pad][4]: unit vectors of r1p - r2p; c: weight of the
-// second Breit term.  Returns the weighted direct and exchange terms.
+// second Breit term.  Returns the weighted direct and exchange terms and,
+// with GRAD, writes the pair's adjoint blocks (FP64) and their Hermitian
+// partners into Hm / Hp as contract_pair does.
+template <bool GRAD = false>
 __device__ __attribute__((always_inline)) inline void contract_pair_breit(const cplx *Gm, const cplx *Gp, int ld, int p, int q, bool ok,
                                            const double *__restrict__ hinv, const double *__restrict__ rhat,
-                                           double c, double wt, double &dir, double &exc) {
+                                           double c, double wt, double &dir, double &exc, double cgrad = 0.0,
+                                           int R = 0, double2 *__restrict__ Hm = nullptr,
+                                           double2 *__restrict__ Hp = nullptr) {
     const int lane = threadIdx.x & 63, l16 = lane & 15, grp = lane & ~15;
 #define GB(G, e, f, i, j) G[(4 * (e) + (i)) * ld + 4 * (f) + (j)]
     const double ux = rhat[4 * p], uy = rhat[4 * p + 1], uz = rhat[4 * p + 2];
     const double vx = rhat[4 * q], vy = rhat[4 * q + 1], vz = rhat[4 * q + 2];
 
     // direct: lane (mu, rho) = (l16 >> 2, l16 & 3) forms T1[mu][rho] and T2[mu][rho]
-    cplx dterm;
+    cplx dterm, T1, U;  // U[mu][rho] = sum_{nu, sig} B12[mu][nu] B34[rho][sig] T2[nu][sig]
     {
         const int mu = l16 >> 2, rho = l16 & 3, xm = sx(mu), xr = sx(rho);
         cplx t1 = {0, 0}, t2 = {0, 0};
@@ -266,6 +327,8 @@ __device__ __attribute__((always_inline)) inline void contract_pair_breit(const 
                 acc = {acc.re + w * t.re, acc.im + w * t.im};
             }
         dterm = cmul(t1, acc);
+        T1 = t1;
+        U = acc;
     }
 
     // exchange: lane (a, b) = (l16 >> 2, l16 & 3) forms element [a][b] of
@@ -318,7 +381,6 @@ __device__ __attribute__((always_inline)) inline void contract_pair_breit(const 
                 xterm = cadd(xterm, cmul(sph(sg, cc, y), rw));
             }
     }
-#undef GB
     for (int mask = 8; mask >= 1; mask >>= 1) {
         dterm = cadd(dterm, shfl_xor_c(dterm, mask));
         xterm = cadd(xterm, shfl_xor_c(xterm, mask));
@@ -328,20 +390,86 @@ __device__ __attribute__((always_inline)) inline void contract_pair_breit(const 
         const double W = hinv[p] * hinv[q] / wt;
         dir = -0.5 * dterm.re * W;
         exc = 0.5 * xterm.re * W;
+        if constexpr (GRAD) {
+            // Adjoint of cw Re(D - X), cw = cgrad W (the Coulomb case's blocks
+            // with the alpha factors and the weights B inserted):
+            //   H-(1,3) = cw (sum U[mu rho] s_mu P13 s_rho - X1)   X1 = sum s_mu P14 K s_rho P23-form (breit_xblock)
+            //   H-(2,4) = cw (sum V[nu sig] s_nu P24 s_sig - X2)
+            //   H+(1,3) = cw sum conj(U[mu rho]) s_mu A13 s_rho     H+(2,4) = cw sum conj(V[nu sig]) s_nu A24 s_sig
+            //   H+(1,4) = -cw X3                                    H+(2,3) = -cw X4
+            // with V[nu][sig] = sum_{mu, rho} B12[mu][nu] B34[rho][sig] T1[mu][rho] and
+            //   X1 = sum s_mu P14 [sum B12[mu nu] B34[rho sig] s_sig A24^H s_nu] P23 s_rho,
+            //   X2 = sum s_nu P23 [sum B12[mu nu] B34[rho sig] s_rho A13^H s_mu] P14 s_sig,
+            //   X3 = sum s_mu A13 [sum B12[mu nu] B34[rho sig] s_rho P23^H s_nu] A24 s_sig,
+            //   X4 = sum s_nu A24 [sum B12[mu nu] B34[rho sig] s_sig P14^H s_mu] A13 s_rho.
+            const double cw = cgrad * W;
+            const int a = l16 >> 2, b = l16 & 3;
+            cplx V = {0, 0};  // lane (nu, sig)
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                for (int rho = 0; rho < 4; ++rho) {
+                    const cplx t = shfl_c(T1, grp | (4 * mu + rho));
+                    const double w = bw(mu, a, ux, uy, uz, c) * bw(rho, b, vx, vy, vz, c);
+                    V = {V.re + w * t.re, V.im + w * t.im};
+                }
+            cplx h13m = {0, 0}, h24m = {0, 0}, h13p = {0, 0}, h24p = {0, 0};
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                for (int rho = 0; rho < 4; ++rho) {
+                    const cplx Um = shfl_c(U, grp | (4 * mu + rho)), Vm = shfl_c(V, grp | (4 * mu + rho));
+                    const int r = a ^ sx(mu), cc = b ^ sx(rho);
+                    // (s_mu Z s_rho)[a][b] = ph(mu, a) Z[a ^ x_mu][b ^ x_rho] ph(rho, b ^ x_rho)
+                    auto ins = [&](const cplx &z) { return sph(mu, a, sph(rho, cc, z)); };
+                    h13m = cadd(h13m, cmul(Um, ins(GB(Gp, 0, 0, r, cc))));
+                    h13p = cadd(h13p, cmul(conjc(Um), ins(GB(Gm, 0, 0, r, cc))));
+                    h24m = cadd(h24m, cmul(Vm, ins(GB(Gp, 1, 1, r, cc))));
+                    h24p = cadd(h24p, cmul(conjc(Vm), ins(GB(Gm, 1, 1, r, cc))));
+                }
+            auto P14 = [&](int i, int j) { return GB(Gp, 0, 1, i, j); };
+            auto P23 = [&](int i, int j) { return GB(Gp, 1, 0, i, j); };
+            auto A13 = [&](int i, int j) { return GB(Gm, 0, 0, i, j); };
+            auto A24 = [&](int i, int j) { return GB(Gm, 1, 1, i, j); };
+            auto A24H = [&](int i, int j) { return conjc(GB(Gm, 1, 1, j, i)); };
+            auto A13H = [&](int i, int j) { return conjc(GB(Gm, 0, 0, j, i)); };
+            auto P23H = [&](int i, int j) { return conjc(GB(Gp, 1, 0, j, i)); };
+            auto P14H = [&](int i, int j) { return conjc(GB(Gp, 0, 1, j, i)); };
+            const cplx x1 = breit_xblock(P14, A24H, P23, l16, ux, uy, uz, vx, vy, vz, c);
+            const cplx x2 = breit_xblock(P23, A13H, P14, l16, ux, uy, uz, vx, vy, vz, c);
+            const cplx x3 = breit_xblock(A13, P23H, A24, l16, ux, uy, uz, vx, vy, vz, c);
+            const cplx x4 = breit_xblock(A24, P14H, A13, l16, ux, uy, uz, vx, vy, vz, c);
+            const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
+            auto put = [&](double2 *H, size_t r, size_t cc, cplx v, double scale) {  // and the Hermitian partner
+                H[r * R + cc] = double2{v.re * scale, v.im * scale};
+                H[cc * R + r] = double2{v.re * scale, -v.im * scale};
+            };
+            put(Hm, r1, c3, csub(h13m, x1), cw);
+            put(Hm, r2, c4, csub(h24m, x2), cw);
+            put(Hp, r1, c3, h13p, cw);
+            put(Hp, r2, c4, h24p, cw);
+            put(Hp, r1, c4, x3, -cw);
+            put(Hp, r2, c3, x4, -cw);
+        }
     }
+#undef GB
 }
 
-// contract_pairs with the Gaunt / Breit interaction (FP64, no gradients).
+// contract_pairs with the Gaunt / Breit interaction (FP64; with GRAD the
+// FP64 adjoint blocks of this tau go to Hm / Hp, R x R).
+template <bool GRAD = false>
 __device__ __attribute__((always_inline)) inline void contract_pairs_breit(const cplx *Gm, const cplx *Gp, int PT, int QT, int m,
                                             const double *__restrict__ hinv, const double *__restrict__ rhat,
-                                            double c, double wt, double *__restrict__ out) {
+                                            double c, double wt, double *__restrict__ out, double cgrad = 0.0,
+                                            int R = 0, double2 *__restrict__ Hm = nullptr,
+                                            double2 *__restrict__ Hp = nullptr) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wp = wave >> 1, wq = wave & 1;
     const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
     const int p = kTileWalkers * PT + 2 * wp + pp, q = kTileWalkers * QT + 2 * wq + qq;
     double dir, exc;
-    contract_pair_breit(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv, rhat,
-                        c, wt, dir, exc);
+    contract_pair_breit<GRAD>(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv,
+                              rhat, c, wt, dir, exc, cgrad, R, Hm, Hp);
     const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
                  d3 = __shfl(dir, 48, 64);
     const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),

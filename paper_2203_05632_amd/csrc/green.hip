@@ -263,10 +263,11 @@ __device__ inline cplx g_entry(const typename GOp<T>::Acc &t1, const typename GO
 // GRAD: also write, per walker pair, the 8x8 blocks of the Hermitian adjoint
 // matrices H- and H+ (gradient of the step value with respect to the entries
 // of G- and G+, folded as Gbar + Gbar^H) into Hm / Hp [n_tau][R][R] complex.
-// BREIT: Gaunt / Breit interaction in the contraction (no gradients; rhat
-// [m_pad][4] unit vectors of r1p - r2p, gauge = weight of the second Breit term).
+// BREIT: Gaunt / Breit interaction in the contraction (rhat [m_pad][4] unit
+// vectors of r1p - r2p, gauge = weight of the second Breit term; with GRAD
+// one tau per block, one wave per SIMD for the adjoint's registers).
 template <typename T, int NT, bool GRAD, bool BREIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD && !BREIT ? 4 : 2))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD && !BREIT ? 4 : (GRAD && BREIT ? 1 : 2)))) void
 green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ scale,
                       const double *__restrict__ wtau, const double *__restrict__ hinv, const int *__restrict__ tiles,
                       const int *__restrict__ work, int n_slots, int R, int no, int nsp, int m,
@@ -333,8 +334,10 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
         // wave barrier orders the staging against the contraction's reads.
         __builtin_amdgcn_wave_barrier();
         if constexpr (BREIT)
-            contract_pairs_breit(Gm, Gp, PT, QT, m, hinv, rhat, gauge, wtau[t0 + t],
-                                 partial + ((size_t)(t0 + t) * n_slots + slot) * 2);
+            contract_pairs_breit<GRAD>(Gm, Gp, PT, QT, m, hinv, rhat, gauge, wtau[t0 + t],
+                                       partial + ((size_t)(t0 + t) * n_slots + slot) * 2, cgrad, R,
+                                       GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
+                                       GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
         else
             contract_pairs<GRAD, double2>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
                                           partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
@@ -440,6 +443,15 @@ namespace {
 template <typename T, int NTV>
 void launch_green_dispatch(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, double cgrad) {
     double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
+    if constexpr (NTV == 1) {
+        if (grad && breit) {
+            const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
+            green_contract_kernel<T, 1, true, true><<<grid, 256, 0, c->stream>>>(
+                c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,
+                c->partial, Hm, Hp, cgrad, c->rhat, gauge);
+            return;
+        }
+    }
     if (grad) {
         green_contract_kernel<T, NTV, true, false><<<grid, 256, 0, c->stream>>>(
             c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,
@@ -482,7 +494,7 @@ hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
     // gradient of the step value (mean over tau of the pair average): c = -1/2 / (mC2 n_tau)
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     const int nblocks = c->n_slots / 4;  // one work-list entry per block, four partial slots
-    const bool breit = c->interaction != MCMP2_COULOMB;  // mcmp2_step rejects gradients with it
+    const bool breit = c->interaction != MCMP2_COULOMB;
     // one tau per block with the Gaunt / Breit contraction: its epilogue
     // needs the registers that a second tau's accumulators would hold
     const int nt = breit ? 1 : green_tau_chunk(nblocks, n_tau, c->n_cu);

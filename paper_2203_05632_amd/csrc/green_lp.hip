@@ -476,7 +476,7 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     uint32_t *Hm = reinterpret_cast<uint32_t *>(c->Hm), *Hp = reinterpret_cast<uint32_t *>(c->Hp);
     const int nblocks = c->n_slots / 4;
-    if (c->interaction != MCMP2_COULOMB) {  // mcmp2_step rejects gradients with it
+    if (c->interaction != MCMP2_COULOMB) {  // no gradients: the step rejects them in these modes
         const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
         const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
         green_lp_kernel<T, 1, false, uint32_t, true><<<dim3(nblocks, n_tau), 256, 0, c->stream>>>(

@@ -218,7 +218,7 @@ def test_step_accumulate_errors():
     with pytest.raises(MCMP2Error) as ei:
         Context.from_inputs(inp).step_accumulate(wk, taus, e2, *acc)      # no want_grad
     assert ei.value.code == -4
-    ctx = _ctx(inp)
+    ctx = _ctx(inp, precision="bf16")
     ctx.set_interaction("breit")
-    with pytest.raises(MCMP2Error, match="Coulomb"):
+    with pytest.raises(MCMP2Error, match="FP64 and FP32"):
         ctx.step_accumulate(wk, taus, e2, *acc)
