@@ -228,95 +228,47 @@ __device__ __forceinline__ double bw(int mu, int nu, double ux, double uy, doubl
     return -0.5 * ((mu == nu ? 1.0 : 0.0) + c * um * un);
 }
 
-// Exchange blocks of the Breit adjoint.  Each has the form
-//   Y = sum_{al, be} s_al L K[al][be] Rm s_be,
-//   K[al][be] = sum_{ga, de} B12[al][ga] B34[be][de] s_de M s_ga
-// (L, M, Rm: 4x4 blocks read through accessors).  Lane (al, be) = (l16 >> 2,
-// l16 & 3) of the pair's group builds its K (s_de M s_ga: M read at permuted
-// indices with phases) and the product (s_al L) K (Rm s_be), the outer
-// alpha factors folded into row / column reads of L and Rm, so every register
-// index is a compile-time one; the 16 entries are then summed over the group
-// (row16_sum) and lane (a, b) = (l16 >> 2, l16 & 3) keeps entry [a][b].
-template <typename FL, typename FM, typename FR>
-__device__ inline cplx breit_xblock(FL L, FM M, FR Rm, int l16, double ux, double uy, double uz, double vx, double vy,
-                                    double vz, double c) {
-    const int al = l16 >> 2, be = l16 & 3, xa = sx(al), xb = sx(be);
-    cplx K[4][4];
+// Direct-part traces of one walker pair for lane (mu, rho) = (l16 >> 2, l16 & 3):
+//   t1 = Tr[A13^H s_mu P13 s_rho],  t2 = Tr[A24^H s_mu P24 s_rho]
+// (16 terms each; tiles as for contract_pair).
+__device__ __attribute__((always_inline)) inline void breit_direct_traces(const cplx *Gm, const cplx *Gp, int ld,
+                                                                           int l16, cplx &t1, cplx &t2) {
+#define GB(G, e, f, i, j) G[(4 * (e) + (i)) * ld + 4 * (f) + (j)]
+    const int mu = l16 >> 2, rho = l16 & 3, xm = sx(mu), xr = sx(rho);
+    t1 = t2 = cplx{0, 0};
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int l = 0; l < 4; ++l) K[k][l] = {0, 0};
-#pragma unroll
-    for (int ga = 0; ga < 4; ++ga)
-#pragma unroll
-        for (int de = 0; de < 4; ++de) {
-            const double w = bw(al, ga, ux, uy, uz, c) * bw(be, de, vx, vy, vz, c);
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    // (s_de M s_ga)[k][l] = ph(de, k) M[k ^ x_de][l ^ x_ga] ph(ga, l ^ x_ga)
-                    const cplx z = sph(de, k, sph(ga, l ^ sx(ga), M(k ^ sx(de), l ^ sx(ga))));
-                    K[k][l] = {K[k][l].re + w * z.re, K[k][l].im + w * z.im};
-                }
+        for (int b = 0; b < 4; ++b) {
+            // Tr[A^H s_mu P s_rho] = sum_{a,b} conj(A[b][a]) ph(mu, b) P[b ^ xm][a ^ xr] ph(rho, a ^ xr)
+            const cplx u1 = sph(mu, b, conjc(GB(Gm, 0, 0, b, a))), u2 = sph(mu, b, conjc(GB(Gm, 1, 1, b, a)));
+            const cplx v1 = sph(rho, a ^ xr, GB(Gp, 0, 0, b ^ xm, a ^ xr));
+            const cplx v2 = sph(rho, a ^ xr, GB(Gp, 1, 1, b ^ xm, a ^ xr));
+            t1 = cadd(t1, cmul(u1, v1));
+            t2 = cadd(t2, cmul(u2, v2));
         }
-    cplx LK[4][4];  // (s_al L)[i][k] = ph(al, i) L[i ^ x_al][k]
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            cplx z = {0, 0};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) z = cadd(z, cmul(L(i ^ xa, k), K[k][l]));
-            LK[i][l] = sph(al, i, z);
-        }
-    cplx mine = {0, 0};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {  // (Rm s_be)[l][j] = Rm[l][j ^ x_be] ph(be, j ^ x_be)
-            cplx z = {0, 0};
-#pragma unroll
-            for (int l = 0; l < 4; ++l) z = cadd(z, cmul(LK[i][l], Rm(l, j ^ xb)));
-            z = row16_sum(sph(be, j ^ xb, z));
-            if (4 * i + j == l16) mine = z;
-        }
-    return mine;
+#undef GB
 }
 
 // One walker pair (p, q) per 16 lanes, tiles as for contract_pair (FP64
 // complex); rhat [m_pad][4]: unit vectors of r1p - r2p; c: weight of the
-// second Breit term.  Returns the weighted direct and exchange terms and,
-// with GRAD, writes the pair's adjoint blocks (FP64) and their Hermitian
-// partners into Hm / Hp as contract_pair does.
-template <bool GRAD = false>
+// second Breit term.  Returns the weighted direct and exchange terms.
 __device__ __attribute__((always_inline)) inline void contract_pair_breit(const cplx *Gm, const cplx *Gp, int ld, int p, int q, bool ok,
                                            const double *__restrict__ hinv, const double *__restrict__ rhat,
-                                           double c, double wt, double &dir, double &exc, double cgrad = 0.0,
-                                           int R = 0, double2 *__restrict__ Hm = nullptr,
-                                           double2 *__restrict__ Hp = nullptr) {
+                                           double c, double wt, double &dir, double &exc) {
     const int lane = threadIdx.x & 63, l16 = lane & 15, grp = lane & ~15;
 #define GB(G, e, f, i, j) G[(4 * (e) + (i)) * ld + 4 * (f) + (j)]
     const double ux = rhat[4 * p], uy = rhat[4 * p + 1], uz = rhat[4 * p + 2];
     const double vx = rhat[4 * q], vy = rhat[4 * q + 1], vz = rhat[4 * q + 2];
 
-    // direct: lane (mu, rho) = (l16 >> 2, l16 & 3) forms T1[mu][rho] and T2[mu][rho]
-    cplx dterm, T1, U;  // U[mu][rho] = sum_{nu, sig} B12[mu][nu] B34[rho][sig] T2[nu][sig]
+    // direct: lane (mu, rho) forms T1[mu][rho] and T2[mu][rho], then
+    // T1[mu][rho] sum_{nu, sig} B12[mu][nu] B34[rho][sig] T2[nu][sig]
+    cplx dterm;
     {
-        const int mu = l16 >> 2, rho = l16 & 3, xm = sx(mu), xr = sx(rho);
-        cplx t1 = {0, 0}, t2 = {0, 0};
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                // Tr[A^H s_mu P s_rho] = sum_{a,b} conj(A[b][a]) ph(mu, b) P[b ^ xm][a ^ xr] ph(rho, a ^ xr)
-                const cplx u1 = sph(mu, b, conjc(GB(Gm, 0, 0, b, a))), u2 = sph(mu, b, conjc(GB(Gm, 1, 1, b, a)));
-                const cplx v1 = sph(rho, a ^ xr, GB(Gp, 0, 0, b ^ xm, a ^ xr));
-                const cplx v2 = sph(rho, a ^ xr, GB(Gp, 1, 1, b ^ xm, a ^ xr));
-                t1 = cadd(t1, cmul(u1, v1));
-                t2 = cadd(t2, cmul(u2, v2));
-            }
-        // sum_{nu, sig} B12[mu][nu] B34[rho][sig] T2[nu][sig], T2 gathered from lane 4 nu + sig
+        const int mu = l16 >> 2, rho = l16 & 3;
+        cplx t1, t2;
+        breit_direct_traces(Gm, Gp, ld, l16, t1, t2);
+        // T2 gathered from lane 4 nu + sig
         cplx acc = {0, 0};
 #pragma unroll
         for (int nu = 0; nu < 4; ++nu)
@@ -327,10 +279,7 @@ __device__ __attribute__((always_inline)) inline void contract_pair_breit(const 
                 acc = {acc.re + w * t.re, acc.im + w * t.im};
             }
         dterm = cmul(t1, acc);
-        T1 = t1;
-        U = acc;
     }
-
     // exchange: lane (a, b) = (l16 >> 2, l16 & 3) forms element [a][b] of
     //   L_{mu sig} = A13^H s_mu P14 s_sig  and element [b][a] of  R_{nu rho} = A24^H s_nu P23 s_rho,
     //   L_{mu sig}[a][b] = ph(sig, b ^ x_sig) sum_k conj(A13[k ^ x_mu][a]) ph(mu, k ^ x_mu) P14[k][b ^ x_sig]
@@ -390,86 +339,21 @@ __device__ __attribute__((always_inline)) inline void contract_pair_breit(const 
         const double W = hinv[p] * hinv[q] / wt;
         dir = -0.5 * dterm.re * W;
         exc = 0.5 * xterm.re * W;
-        if constexpr (GRAD) {
-            // Adjoint of cw Re(D - X), cw = cgrad W (the Coulomb case's blocks
-            // with the alpha factors and the weights B inserted):
-            //   H-(1,3) = cw (sum U[mu rho] s_mu P13 s_rho - X1)   X1 = sum s_mu P14 K s_rho P23-form (breit_xblock)
-            //   H-(2,4) = cw (sum V[nu sig] s_nu P24 s_sig - X2)
-            //   H+(1,3) = cw sum conj(U[mu rho]) s_mu A13 s_rho     H+(2,4) = cw sum conj(V[nu sig]) s_nu A24 s_sig
-            //   H+(1,4) = -cw X3                                    H+(2,3) = -cw X4
-            // with V[nu][sig] = sum_{mu, rho} B12[mu][nu] B34[rho][sig] T1[mu][rho] and
-            //   X1 = sum s_mu P14 [sum B12[mu nu] B34[rho sig] s_sig A24^H s_nu] P23 s_rho,
-            //   X2 = sum s_nu P23 [sum B12[mu nu] B34[rho sig] s_rho A13^H s_mu] P14 s_sig,
-            //   X3 = sum s_mu A13 [sum B12[mu nu] B34[rho sig] s_rho P23^H s_nu] A24 s_sig,
-            //   X4 = sum s_nu A24 [sum B12[mu nu] B34[rho sig] s_sig P14^H s_mu] A13 s_rho.
-            const double cw = cgrad * W;
-            const int a = l16 >> 2, b = l16 & 3;
-            cplx V = {0, 0};  // lane (nu, sig)
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int rho = 0; rho < 4; ++rho) {
-                    const cplx t = shfl_c(T1, grp | (4 * mu + rho));
-                    const double w = bw(mu, a, ux, uy, uz, c) * bw(rho, b, vx, vy, vz, c);
-                    V = {V.re + w * t.re, V.im + w * t.im};
-                }
-            cplx h13m = {0, 0}, h24m = {0, 0}, h13p = {0, 0}, h24p = {0, 0};
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int rho = 0; rho < 4; ++rho) {
-                    const cplx Um = shfl_c(U, grp | (4 * mu + rho)), Vm = shfl_c(V, grp | (4 * mu + rho));
-                    const int r = a ^ sx(mu), cc = b ^ sx(rho);
-                    // (s_mu Z s_rho)[a][b] = ph(mu, a) Z[a ^ x_mu][b ^ x_rho] ph(rho, b ^ x_rho)
-                    auto ins = [&](const cplx &z) { return sph(mu, a, sph(rho, cc, z)); };
-                    h13m = cadd(h13m, cmul(Um, ins(GB(Gp, 0, 0, r, cc))));
-                    h13p = cadd(h13p, cmul(conjc(Um), ins(GB(Gm, 0, 0, r, cc))));
-                    h24m = cadd(h24m, cmul(Vm, ins(GB(Gp, 1, 1, r, cc))));
-                    h24p = cadd(h24p, cmul(conjc(Vm), ins(GB(Gm, 1, 1, r, cc))));
-                }
-            auto P14 = [&](int i, int j) { return GB(Gp, 0, 1, i, j); };
-            auto P23 = [&](int i, int j) { return GB(Gp, 1, 0, i, j); };
-            auto A13 = [&](int i, int j) { return GB(Gm, 0, 0, i, j); };
-            auto A24 = [&](int i, int j) { return GB(Gm, 1, 1, i, j); };
-            auto A24H = [&](int i, int j) { return conjc(GB(Gm, 1, 1, j, i)); };
-            auto A13H = [&](int i, int j) { return conjc(GB(Gm, 0, 0, j, i)); };
-            auto P23H = [&](int i, int j) { return conjc(GB(Gp, 1, 0, j, i)); };
-            auto P14H = [&](int i, int j) { return conjc(GB(Gp, 0, 1, j, i)); };
-            const cplx x1 = breit_xblock(P14, A24H, P23, l16, ux, uy, uz, vx, vy, vz, c);
-            const cplx x2 = breit_xblock(P23, A13H, P14, l16, ux, uy, uz, vx, vy, vz, c);
-            const cplx x3 = breit_xblock(A13, P23H, A24, l16, ux, uy, uz, vx, vy, vz, c);
-            const cplx x4 = breit_xblock(A24, P14H, A13, l16, ux, uy, uz, vx, vy, vz, c);
-            const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
-            auto put = [&](double2 *H, size_t r, size_t cc, cplx v, double scale) {  // and the Hermitian partner
-                H[r * R + cc] = double2{v.re * scale, v.im * scale};
-                H[cc * R + r] = double2{v.re * scale, -v.im * scale};
-            };
-            put(Hm, r1, c3, csub(h13m, x1), cw);
-            put(Hm, r2, c4, csub(h24m, x2), cw);
-            put(Hp, r1, c3, h13p, cw);
-            put(Hp, r2, c4, h24p, cw);
-            put(Hp, r1, c4, x3, -cw);
-            put(Hp, r2, c3, x4, -cw);
-        }
     }
 #undef GB
 }
 
-// contract_pairs with the Gaunt / Breit interaction (FP64; with GRAD the
-// FP64 adjoint blocks of this tau go to Hm / Hp, R x R).
-template <bool GRAD = false>
+// contract_pairs with the Gaunt / Breit interaction (FP64).
 __device__ __attribute__((always_inline)) inline void contract_pairs_breit(const cplx *Gm, const cplx *Gp, int PT, int QT, int m,
                                             const double *__restrict__ hinv, const double *__restrict__ rhat,
-                                            double c, double wt, double *__restrict__ out, double cgrad = 0.0,
-                                            int R = 0, double2 *__restrict__ Hm = nullptr,
-                                            double2 *__restrict__ Hp = nullptr) {
+                                            double c, double wt, double *__restrict__ out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wp = wave >> 1, wq = wave & 1;
     const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
     const int p = kTileWalkers * PT + 2 * wp + pp, q = kTileWalkers * QT + 2 * wq + qq;
     double dir, exc;
-    contract_pair_breit<GRAD>(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv,
-                              rhat, c, wt, dir, exc, cgrad, R, Hm, Hp);
+    contract_pair_breit(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv, rhat,
+                        c, wt, dir, exc);
     const double d0 = __shfl(dir, 0, 64), d1 = __shfl(dir, 16, 64), d2 = __shfl(dir, 32, 64),
                  d3 = __shfl(dir, 48, 64);
     const double x0 = __shfl(exc, 0, 64), x1 = __shfl(exc, 16, 64), x2 = __shfl(exc, 32, 64),
@@ -478,6 +362,189 @@ __device__ __attribute__((always_inline)) inline void contract_pairs_breit(const
         out[0] = ((d0 + d1) + d2) + d3;
         out[1] = ((x0 + x1) + x2) + x3;
     }
+}
+
+// ph(mu, b) as a power of i (sph multiplies by i^qph)
+__device__ __forceinline__ int qph(int mu, int b) { return mu == 2 ? ((b & 1) ? 1 : 3) : (mu == 3 ? ((b & 1) ? 2 : 0) : 0); }
+// i^q z
+__device__ __forceinline__ cplx qrot(cplx z, int q) {
+    const cplx s = (q & 1) ? cplx{-z.im, z.re} : z;
+    return (q & 2) ? cplx{-s.re, -s.im} : s;
+}
+
+// Sum over the 16 lanes of a row of the 16 values v[e], lane l16 of the row
+// ending with the sum of v[l16]: four halving steps, each lane keeping the
+// half of its values whose index bit matches its own lane bit (3, 2, 1, 0)
+// and adding the partner's copy of that half (partners: row_ror:8,
+// row_half_mirror, xor 2, xor 1 -- each flips the step's bit and none of the
+// bits above it).
+__device__ inline cplx row16_reduce_scatter(const cplx (&v)[16], int l16) {
+    const bool b3 = l16 & 8, b2 = l16 & 4, b1 = l16 & 2, b0 = l16 & 1;
+    cplx r8[8], r4[4], r2[2];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const cplx send = b3 ? v[n] : v[n + 8], keep = b3 ? v[n + 8] : v[n];
+        r8[n] = cadd(keep, dpp_c<0x128>(send));
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const cplx send = b2 ? r8[n] : r8[n + 4], keep = b2 ? r8[n + 4] : r8[n];
+        r4[n] = cadd(keep, dpp_c<0x141>(send));
+    }
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const cplx send = b1 ? r4[n] : r4[n + 2], keep = b1 ? r4[n + 2] : r4[n];
+        r2[n] = cadd(keep, dpp_c<0x4E>(send));
+    }
+    const cplx send = b0 ? r2[0] : r2[1], keep = b0 ? r2[1] : r2[0];
+    return cadd(keep, dpp_c<0xB1>(send));
+}
+
+// Exchange blocks of the Breit adjoint.  Each has the form
+//   Y = sum_{al, be} s_al L K[al][be] Rm s_be,
+//   K[al][be] = sum_{ga, de} B12[al][ga] B34[be][de] s_de M s_ga = S2(be) M S1(al),
+//   S1(al) = sum_ga B12[al][ga] s_ga,  S2(be) = sum_de B34[be][de] s_de
+// (L, M, Rm: 4x4 blocks read through accessors; b1[ga] = B12[al][ga] and
+// b2[de] = B34[be][de] of this lane).  Lane (al, be) = (l16 >> 2, l16 & 3) of
+// the pair's group forms its term (s_al L) K (Rm s_be) -- the alpha factors
+// as permuted reads and phases, every register index a compile-time one --
+// and the 16 terms are summed, lane (a, b) keeping entry [a][b].
+template <typename FL, typename FM, typename FR>
+__device__ inline cplx breit_xblock(FL L, FM M, FR Rm, int l16, const double (&b1)[4], const double (&b2)[4]) {
+    const int al = l16 >> 2, be = l16 & 3, xa = sx(al), xb = sx(be);
+    cplx N[4][4];  // M S1: (M s_ga)[r][l] = M[r][l ^ x_ga] ph(ga, l ^ x_ga)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            cplx z = {0, 0};
+#pragma unroll
+            for (int ga = 0; ga < 4; ++ga) {
+                const cplx t = sph(ga, l ^ sx(ga), M(r, l ^ sx(ga)));
+                z = {z.re + b1[ga] * t.re, z.im + b1[ga] * t.im};
+            }
+            N[r][l] = z;
+        }
+    cplx K[4][4];  // S2 N: (s_de N)[k][l] = ph(de, k) N[k ^ x_de][l]
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            cplx z = {0, 0};
+#pragma unroll
+            for (int de = 0; de < 4; ++de) {
+                const cplx t = sph(de, k, N[k ^ sx(de)][l]);
+                z = {z.re + b2[de] * t.re, z.im + b2[de] * t.im};
+            }
+            K[k][l] = z;
+        }
+    cplx LK[4][4];  // L[i ^ x_al][.] K; the phase ph(al, i) of s_al goes on the result
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            cplx z = {0, 0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) z = cadd(z, cmul(L(i ^ xa, k), K[k][l]));
+            LK[i][l] = z;
+        }
+    cplx y[16];  // (Rm s_be)[l][j] = Rm[l][j ^ x_be] ph(be, j ^ x_be)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cplx z = {0, 0};
+#pragma unroll
+            for (int l = 0; l < 4; ++l) z = cadd(z, cmul(LK[i][l], Rm(l, j ^ xb)));
+            y[4 * i + j] = qrot(z, qph(al, i) + qph(be, j ^ xb));
+        }
+    return row16_reduce_scatter(y, l16);
+}
+
+// Adjoint of one walker pair's Gaunt / Breit terms (16 lanes, tiles as for
+// contract_pair): writes the pair's six 4x4 blocks of H- and H+ (FP64) and
+// their Hermitian partners, as contract_pair<true> does for the Coulomb
+// interaction; ok = false writes nothing.  With cw = cgrad W:
+//   H-(1,3) = cw (sum_{mu rho} U[mu][rho] s_mu P13 s_rho - X1)
+//   H-(2,4) = cw (sum_{nu sig} V[nu][sig] s_nu P24 s_sig - X2)
+//   H+(1,3) = cw sum conj(U[mu][rho]) s_mu A13 s_rho,  H+(2,4) = cw sum conj(V[nu][sig]) s_nu A24 s_sig
+//   H+(1,4) = -cw X3,  H+(2,3) = -cw X4
+// with U[mu][rho] = sum B12[mu][nu] B34[rho][sig] T2[nu][sig] and
+// V[nu][sig] = sum B12[mu][nu] B34[rho][sig] T1[mu][rho] (T1, T2: the direct
+// traces), and the exchange blocks (breit_xblock)
+//   X1 = sum s_mu P14 [sum B12[mu nu] B34[rho sig] s_sig A24^H s_nu] P23 s_rho,
+//   X2 = sum s_nu P23 [sum B12[mu nu] B34[rho sig] s_rho A13^H s_mu] P14 s_sig,
+//   X3 = sum s_mu A13 [sum B12[mu nu] B34[rho sig] s_rho P23^H s_nu] A24 s_sig,
+//   X4 = sum s_nu A24 [sum B12[mu nu] B34[rho sig] s_sig P14^H s_mu] A13 s_rho.
+__device__ inline void breit_adjoint_pair(const cplx *Gm, const cplx *Gp, int ld, int p, int q, bool ok,
+                                          const double *__restrict__ hinv, const double *__restrict__ rhat, double c,
+                                          double wt, double cgrad, int R, double2 *__restrict__ Hm,
+                                          double2 *__restrict__ Hp) {
+    if (!ok) return;  // ok is the same in all 16 lanes of the pair
+    const int lane = threadIdx.x & 63, l16 = lane & 15, grp = lane & ~15;
+    const int a = l16 >> 2, b = l16 & 3;
+#define GB(G, e, f, i, j) G[(4 * (e) + (i)) * ld + 4 * (f) + (j)]
+    const double ux = rhat[4 * p], uy = rhat[4 * p + 1], uz = rhat[4 * p + 2];
+    const double vx = rhat[4 * q], vy = rhat[4 * q + 1], vz = rhat[4 * q + 2];
+    double b1[4], b2[4];  // B12[a][.], B34[b][.] of this lane
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        b1[g] = bw(a, g, ux, uy, uz, c);
+        b2[g] = bw(b, g, vx, vy, vz, c);
+    }
+    cplx t1, t2;
+    breit_direct_traces(Gm, Gp, ld, l16, t1, t2);
+    cplx U = {0, 0}, V = {0, 0};  // lane (a, b): U[a][b], V[a][b]
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const double w = b1[e] * b2[f];
+            const cplx s2 = shfl_c(t2, grp | (4 * e + f)), s1 = shfl_c(t1, grp | (4 * e + f));
+            U = {U.re + w * s2.re, U.im + w * s2.im};
+            V = {V.re + w * s1.re, V.im + w * s1.im};
+        }
+    const double cw = cgrad * hinv[p] * hinv[q] / wt;
+    cplx h13m = {0, 0}, h24m = {0, 0}, h13p = {0, 0}, h24p = {0, 0};
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int rho = 0; rho < 4; ++rho) {
+            const cplx Um = shfl_c(U, grp | (4 * mu + rho)), Vm = shfl_c(V, grp | (4 * mu + rho));
+            const int r = a ^ sx(mu), cc = b ^ sx(rho);
+            // (s_mu Z s_rho)[a][b] = ph(mu, a) Z[a ^ x_mu][b ^ x_rho] ph(rho, b ^ x_rho)
+            const int qp = qph(mu, a) + qph(rho, cc);
+            h13m = cadd(h13m, cmul(Um, qrot(GB(Gp, 0, 0, r, cc), qp)));
+            h13p = cadd(h13p, cmul(conjc(Um), qrot(GB(Gm, 0, 0, r, cc), qp)));
+            h24m = cadd(h24m, cmul(Vm, qrot(GB(Gp, 1, 1, r, cc), qp)));
+            h24p = cadd(h24p, cmul(conjc(Vm), qrot(GB(Gm, 1, 1, r, cc), qp)));
+        }
+    const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
+    auto put = [&](double2 *H, size_t r, size_t cc, cplx v, double scale) {  // and the Hermitian partner
+        H[r * R + cc] = double2{v.re * scale, v.im * scale};
+        H[cc * R + r] = double2{v.re * scale, -v.im * scale};
+    };
+    put(Hp, r1, c3, h13p, cw);
+    put(Hp, r2, c4, h24p, cw);
+    // the four exchange blocks in one loop (not unrolled: one block's registers at a time);
+    // L and Rm are plain 4x4 blocks, M a conjugate-transposed one:
+    //   X1: (P14, A24, P23)  X2: (P23, A13, P14)  X3: (A13, P23, A24)  X4: (A24, P14, A13)
+#pragma nounroll
+    for (int x = 0; x < 4; ++x) {
+        const cplx *Lb = x == 0 ? &GB(Gp, 0, 1, 0, 0) : x == 1 ? &GB(Gp, 1, 0, 0, 0) : x == 2 ? &GB(Gm, 0, 0, 0, 0)
+                                                                                        : &GB(Gm, 1, 1, 0, 0);
+        const cplx *Mb = x == 0 ? &GB(Gm, 1, 1, 0, 0) : x == 1 ? &GB(Gm, 0, 0, 0, 0) : x == 2 ? &GB(Gp, 1, 0, 0, 0)
+                                                                                        : &GB(Gp, 0, 1, 0, 0);
+        const cplx *Rb = x == 0 ? &GB(Gp, 1, 0, 0, 0) : x == 1 ? &GB(Gp, 0, 1, 0, 0) : x == 2 ? &GB(Gm, 1, 1, 0, 0)
+                                                                                        : &GB(Gm, 0, 0, 0, 0);
+        const cplx y = breit_xblock([&](int i, int j) { return Lb[i * ld + j]; },
+                                    [&](int i, int j) { return conjc(Mb[j * ld + i]); },
+                                    [&](int i, int j) { return Rb[i * ld + j]; }, l16, b1, b2);
+        // X1 -> H-(1,3), X2 -> H-(2,4) (with the direct sums), X3 -> H+(1,4), X4 -> H+(2,3)
+        const cplx h = x == 0 ? csub(h13m, y) : x == 1 ? csub(h24m, y) : y;
+        put(x < 2 ? Hm : Hp, (x & 1) ? r2 : r1, x == 0 || x == 3 ? c3 : c4, h, x < 2 ? cw : -cw);
+    }
+#undef GB
 }
 
 // One wave, one tau sample.  Gm / Gp: this wave's 16x16 sub-tiles of G- and

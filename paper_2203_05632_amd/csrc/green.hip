@@ -264,10 +264,12 @@ __device__ inline cplx g_entry(const typename GOp<T>::Acc &t1, const typename GO
 // matrices H- and H+ (gradient of the step value with respect to the entries
 // of G- and G+, folded as Gbar + Gbar^H) into Hm / Hp [n_tau][R][R] complex.
 // BREIT: Gaunt / Breit interaction in the contraction (rhat [m_pad][4] unit
-// vectors of r1p - r2p, gauge = weight of the second Breit term; with GRAD
-// one tau per block, one wave per SIMD for the adjoint's registers).
+// vectors of r1p - r2p, gauge = weight of the second Breit term; one tau per
+// block).  With GRAD and BREIT the kernel copies, for every pair p < q < m,
+// G-(1,3), G-(2,4) and the four 4x4 blocks of G+ into the pair's blocks of
+// Hm / Hp instead, for breit_adjoint_kernel.
 template <typename T, int NT, bool GRAD, bool BREIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD && !BREIT ? 4 : (GRAD && BREIT ? 1 : 2)))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 && !GRAD && !BREIT ? 4 : 2))) void
 green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ scale,
                       const double *__restrict__ wtau, const double *__restrict__ hinv, const int *__restrict__ tiles,
                       const int *__restrict__ work, int n_slots, int R, int no, int nsp, int m,
@@ -326,18 +328,27 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = O::row(v, lk);
+            const cplx gp = g_entry<T>(p1[t], p2[t], p3[t], v);
             Gm[i * 16 + li] = gm[t][v];
-            Gp[i * 16 + li] = g_entry<T>(p1[t], p2[t], p3[t], v);
+            Gp[i * 16 + li] = gp;
+            if constexpr (GRAD && BREIT) {
+                const int row = rp + 16 * (wave >> 1) + i, col = rq + 16 * (wave & 1) + li;
+                if ((row >> 3) < (col >> 3) && (col >> 3) < m) {
+                    // G- only in its (1,3) and (2,4) blocks: the adjoint reads and
+                    // overwrites those, and H-(1,4), H-(2,3) stay zero
+                    const size_t o = (size_t)(t0 + t) * R * R + (size_t)row * R + col;
+                    if (((row ^ col) & 4) == 0) Hm[o] = double2{gm[t][v].re, gm[t][v].im};
+                    Hp[o] = double2{gp.re, gp.im};
+                }
+            }
         }
         // The staged sub-tiles are private to the wave (the K loop ended with a
         // block barrier) and one wave's LDS accesses complete in order, so a
         // wave barrier orders the staging against the contraction's reads.
         __builtin_amdgcn_wave_barrier();
         if constexpr (BREIT)
-            contract_pairs_breit<GRAD>(Gm, Gp, PT, QT, m, hinv, rhat, gauge, wtau[t0 + t],
-                                       partial + ((size_t)(t0 + t) * n_slots + slot) * 2, cgrad, R,
-                                       GRAD ? Hm + (size_t)(t0 + t) * R * R : nullptr,
-                                       GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
+            contract_pairs_breit(Gm, Gp, PT, QT, m, hinv, rhat, gauge, wtau[t0 + t],
+                                 partial + ((size_t)(t0 + t) * n_slots + slot) * 2);
         else
             contract_pairs<GRAD, double2>(Gm, Gp, PT, QT, m, hinv, wtau[t0 + t], cgrad, R,
                                           partial + ((size_t)(t0 + t) * n_slots + slot) * 2,
@@ -345,6 +356,46 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
                                           GRAD ? Hp + (size_t)(t0 + t) * R * R : nullptr);
         __builtin_amdgcn_wave_barrier();  // the sub-tiles are rewritten for the next tau
     }
+}
+
+// Adjoint of the Gaunt / Breit contraction.  Grid as green_contract_kernel's
+// with one tau per block row (x: work-list entry, y: tau); wave (wp, wq) takes
+// the same 16x16 sub-tiles and walker pairs.  On entry Hm / Hp [n_tau][R][R]
+// hold, in the 8x8 blocks of the pairs p < q < m, G-(1,3), G-(2,4) (H-(1,4)
+// and H-(2,3) are zero, as everywhere) and all of G+ (written by the Green's
+// kernel); each pair reads its own blocks and overwrites those with its
+// adjoint blocks, writing their Hermitian partners into the (q, p) blocks,
+// which no pair reads.  Diagonal and padding blocks are never written.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void
+breit_adjoint_kernel(double2 *__restrict__ Hm, double2 *__restrict__ Hp, const double *__restrict__ wtau,
+                     const double *__restrict__ hinv, const int *__restrict__ tiles, const int *__restrict__ work,
+                     int R, int m, double cgrad, const double *__restrict__ rhat, double gauge) {
+    __shared__ __align__(16) cplx sg[4][2][256];
+    const int item = work[blockIdx.x];
+    if (item < 0) return;
+    const int t = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wp = wave >> 1, wq = wave & 1;
+    const int PT = tiles[2 * item], QT = tiles[2 * item + 1];
+    const int p0 = kTileWalkers * PT + 2 * wp, q0 = kTileWalkers * QT + 2 * wq;
+    if (p0 >= q0 + 1 || q0 >= m) return;  // no pair p < q < m in this wave's sub-tile
+    double2 *hm = Hm + (size_t)t * R * R, *hp = Hp + (size_t)t * R * R;
+    cplx *Gm = sg[wave][0], *Gp = sg[wave][1];
+    const int li = lane & 15, lk = lane >> 4;
+    const size_t r0 = 8 * (size_t)p0, c0 = 8 * (size_t)q0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + lk;
+        const size_t o = (r0 + i) * R + c0 + li;
+        const double2 x = hm[o], y = hp[o];
+        Gm[i * 16 + li] = cplx{x.x, x.y};
+        Gp[i * 16 + li] = cplx{y.x, y.y};
+    }
+    // the sub-tiles are private to the wave, whose LDS accesses complete in order
+    __builtin_amdgcn_wave_barrier();
+    const int pi = lane >> 4, pp = pi >> 1, qq = pi & 1;
+    const int p = p0 + pp, q = q0 + qq;
+    breit_adjoint_pair(Gm + 8 * pp * 16 + 8 * qq, Gp + 8 * pp * 16 + 8 * qq, 16, p, q, p < q && q < m, hinv, rhat,
+                       gauge, wtau[t], cgrad, R, hm, hp);
 }
 
 // One block per tau sample.
@@ -444,11 +495,13 @@ template <typename T, int NTV>
 void launch_green_dispatch(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit, double cgrad) {
     double2 *Hm = reinterpret_cast<double2 *>(c->Hm), *Hp = reinterpret_cast<double2 *>(c->Hp);
     if constexpr (NTV == 1) {
-        if (grad && breit) {
+        if (grad && breit) {  // G blocks to Hm / Hp, then their adjoint in place
             const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
             green_contract_kernel<T, 1, true, true><<<grid, 256, 0, c->stream>>>(
                 c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,
                 c->partial, Hm, Hp, cgrad, c->rhat, gauge);
+            breit_adjoint_kernel<<<grid, 256, 0, c->stream>>>(Hm, Hp, c->wtau, c->hinv, c->tiles, c->work, c->R, c->m,
+                                                               cgrad, c->rhat, gauge);
             return;
         }
     }

@@ -208,3 +208,26 @@ def test_breit_gradients_rejected_in_bf16_fp16():
         with pytest.raises(MCMP2Error, match="FP64 and FP32"):
             ctx.step(wk, dev([0.3]), e2, grad_eps=ge)
         ctx.step(wk, dev([0.3]), e2)  # forward only is fine
+
+
+def test_breit_gradients_switching_interactions_bitwise():
+    """Coulomb, Breit, Gaunt and Coulomb gradient steps on one context give
+    bit for bit the gradients of fresh contexts: the Breit path leaves no block
+    of the shared adjoint buffers that a later step of another kind would read
+    (it writes exactly the Coulomb adjoint's blocks)."""
+    inp = make_inputs("C0", m=13, n_occ=6, n_vir=10, n_tau=3)
+    wk = initial_walkers(inp)
+    taus = np.array([0.2, 0.7, 2.5])
+
+    def fresh(kind):
+        ctx = _ctx(inp, want_grad=True)
+        ctx.set_interaction(kind)
+        return _gpu_grad(ctx, inp, wk, taus)
+
+    ref = {k: fresh(k) for k in ("coulomb", "breit", "gaunt")}
+    ctx = _ctx(inp, want_grad=True)
+    for kind in ("coulomb", "breit", "gaunt", "coulomb"):
+        ctx.set_interaction(kind)
+        got = _gpu_grad(ctx, inp, wk, taus)
+        for x, y in zip(got, ref[kind]):
+            assert np.array_equal(x, y), kind
