@@ -48,7 +48,14 @@ __device__ inline int swz(int row, int unit) { return row * 8 + (unit ^ (row & 7
 // Work items (row tile, column tile), row-tile major, are dealt to the XCDs
 // in contiguous ranges (block b runs on XCD b % 8), so that blocks sharing
 // H rows or V columns run side by side on one L2.
-template <int WN, int NCW>
+// DMA: chunks go from global memory straight into a ring of three LDS stages
+// (global_load_lds_dwordx4, issued two chunks ahead; no staging registers),
+// waited for with an explicit vmcnt: the compiler does not track these loads,
+// so it inserts no wait of its own before the LDS reads (with the load builtin
+// it waits for every outstanding load there).  Vector-memory loads complete in
+// issue order, so a wait the compiler places for its own later loads also
+// covers these.
+template <int WN, int NCW, bool DMA>
 __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     const uint32_t *__restrict__ Hm, const uint32_t *__restrict__ Hp, const uint32_t *__restrict__ V,
     const float2 *__restrict__ psi, const double *__restrict__ tau, int n_tau, int R, int no, int nsp,
@@ -57,7 +64,8 @@ __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     constexpr int NTH = 128 * NCW, BN = NCW * WN, NJ = WN / 16;
     constexpr int NA = ABM * (AK / 4) / NTH;  // 16-byte A units per thread per chunk
     constexpr int NB = BN * (AK / 4) / NTH;   // 16-byte B units per thread per chunk
-    __shared__ __align__(16) uint32_t lds[2][(ABM + BN) * AK];
+    constexpr int NST = DMA ? 3 : 2;
+    __shared__ __align__(16) uint32_t lds[NST][(ABM + BN) * AK];
     __shared__ float dpart[2][BN];
 
     const int per = (n_items + 7) / 8;
@@ -161,16 +169,58 @@ __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
         }
     };
 
-    gload(ra, rb, 0);
-    lstore(ra, rb, 0);
-    __syncthreads();
-    for (int c = 0; c < n_chunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < n_chunks) gload(ra, rb, c + 1);
-        compute(buf);
-        if (c + 1 < n_chunks) lstore(ra, rb, buf ^ 1);
-        tau_boundary(c);
+    if constexpr (DMA) {
+        // wave w fills the 8-row groups g = w + NW j of a stage, one 16-byte unit
+        // per lane: row 8 g + lane / 8 at slot lane % 8, i.e. global unit
+        // (lane % 8) ^ (row & 7) (the swizzle of swz)
+        constexpr int NW = 2 * NCW, NG = (ABM + BN) / 8 / NW, NGA = ABM / 8 / NW;
+        static_assert((ABM + BN) % (8 * NW) == 0 && ABM % (8 * NW) == 0, "row groups per wave");
+        constexpr uint32_t STAGE = (ABM + BN) * AK * 4;
+        const uint32_t *dsrc[NG];
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            const int row = 8 * (wave + NW * j) + lane / 8, unit = (lane & 7) ^ (row & 7);
+            dsrc[j] = j < NGA ? H + (size_t)min(x0 + row, R - 1) * R + 4 * unit
+                              : V + (size_t)min(k0 + row - ABM, k_hi - 1) * R + 4 * unit;
+        }
+        const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)(&lds[0][0]);
+        auto dma = [&](int c) __attribute__((always_inline)) {
+            const int t = c / cpt, y0 = (c % cpt) * AK;
+            const uint32_t base = lds0 + (uint32_t)(c % 3) * STAGE;
+#pragma unroll
+            for (int j = 0; j < NG; ++j) {
+                const uint32_t *g = dsrc[j] + (j < NGA ? t * RR : t * NR) + y0;
+                const uint32_t m0v = __builtin_amdgcn_readfirstlane(base + 1024u * (uint32_t)(wave + NW * j));
+                asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v), "v"(g)
+                             : "memory");
+            }
+        };
+        dma(0);
+        if (n_chunks > 1) dma(1);
+        for (int c = 0; c < n_chunks; ++c) {
+            // this wave's loads of chunk c are done once at most the NG of chunk c + 1 are out
+            if (c + 1 < n_chunks)
+                asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NG) : "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();  // every wave's chunk c is in LDS and every wave is done with chunk c - 1
+            if (c + 2 < n_chunks) dma(c + 2);  // into the stage chunk c - 1 used
+            compute(c % 3);
+            tau_boundary(c);
+        }
         __syncthreads();
+    } else {
+        gload(ra, rb, 0);
+        lstore(ra, rb, 0);
+        __syncthreads();
+        for (int c = 0; c < n_chunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < n_chunks) gload(ra, rb, c + 1);
+            compute(buf);
+            if (c + 1 < n_chunks) lstore(ra, rb, buf ^ 1);
+            tau_boundary(c);
+            __syncthreads();
+        }
     }
 
     // Psibar tile -> the coefficient gradient's BF16 operand PBb[set][4 k + 2 s + ri][pt]
@@ -208,7 +258,7 @@ __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     if (tid < BN && k0 + tid < k_hi) eps_part[(size_t)rt * nsp + k0 + tid] = e_acc;
 }
 
-template <int WN, int NCW>
+template <int WN, int NCW, bool DMA = false>
 hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
     constexpr int BN = NCW * WN;
     const int n_occ_tiles = (c->no + BN - 1) / BN, n_vir_tiles = (c->nsp - c->no + BN - 1) / BN;
@@ -217,7 +267,7 @@ hipError_t launch_adj_typed(const mcmp2_ctx *c, const double *tau, int n_tau) {
     const int n_items = n_row_tiles * n_col_tiles;
     const int per = (n_items + 7) / 8;
     const int ps = prof_begin(c, MCMP2_K_ADJ_GEMM);
-    adj_lp_kernel<WN, NCW><<<8 * per, 128 * NCW, 0, c->stream>>>(
+    adj_lp_kernel<WN, NCW, DMA><<<8 * per, 128 * NCW, 0, c->stream>>>(
         reinterpret_cast<const uint32_t *>(c->Hm), reinterpret_cast<const uint32_t *>(c->Hp), c->Vt,
         reinterpret_cast<const float2 *>(c->psi), tau, n_tau, c->R, c->no, c->nsp, n_occ_tiles, n_col_tiles, n_items,
         c->Ep, reinterpret_cast<unsigned short *>(c->PBb), c->eps_part);
@@ -238,6 +288,6 @@ hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau) {
     // narrower tiles' extra blocks win (128 pairs: 32 tiles, 101 against 67 us)
     const int wide_items = ((c->R + ABM - 1) / ABM) * ((c->no + 127) / 128 + (c->nsp - c->no + 127) / 128);
     const int wider_items = ((c->R + ABM - 1) / ABM) * ((c->no + 255) / 256 + (c->nsp - c->no + 255) / 256);
-    if (4 * wider_items >= 3 * c->n_cu) return launch_adj_typed<64, 4>(c, tau, n_tau);
+    if (4 * wider_items >= 3 * c->n_cu) return launch_adj_typed<64, 4, true>(c, tau, n_tau);
     return wide_items >= c->n_cu ? launch_adj_typed<64, 2>(c, tau, n_tau) : launch_adj_typed<32, 2>(c, tau, n_tau);
 }
