@@ -309,6 +309,12 @@ __device__ inline f4v mfma_pair(u32x4 a, u32x4 b, f4v c) {
                                                       0, 0);
 }
 
+// K chunks reach LDS by direct global -> LDS loads into a ring of three stages
+// (global_load_lds_dwordx4, two chunks ahead, explicit vmcnt waits: the
+// compiler does not track these loads, so it adds no waits of its own before
+// the LDS reads); otherwise by two register stages into two LDS stages.
+constexpr bool kBigDma = true;
+
 template <typename T, bool GRAD>
 __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restrict__ U, int Kow, int Ktw,
                                                         const double *__restrict__ wtau,
@@ -318,7 +324,8 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
                                                         uint32_t *__restrict__ Hm, uint32_t *__restrict__ Hp,
                                                         double cgrad) {
     constexpr int STAGE = 2 * BT * BKW;  // words per stage: A rows then B rows
-    __shared__ __align__(16) uint32_t lds[2 * STAGE];
+    constexpr int NST = kBigDma ? 3 : 2;
+    __shared__ __align__(16) uint32_t lds[NST * STAGE];
     const int per = (n_items + 7) / 8;
     const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (item >= n_items) return;
@@ -372,9 +379,45 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
             }
         }
     };
+    // direct loads: wave w fills the 8-row groups g = w + 8 j of a stage (j < 2: rows of P,
+    // j >= 2: rows of Q), one 16-byte unit per lane: row 8 g + lane / 8 at slot lane % 8,
+    // i.e. global unit (lane % 8) ^ (row & 7) (the swizzle of swz)
+    const uint32_t *dsrc[4];
+    for (int j = 0; j < 4; ++j) {
+        const int row = 8 * (wave + 8 * j) + lane / 8, unit = (lane & 7) ^ (row & 7);
+        const int grow = row < BT ? BT * P + row : BT * Q + (row - BT);
+        dsrc[j] = Ut + (size_t)min(grow, R - 1) * Ktw + 4 * unit;
+    }
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)(&lds[0]);
+    auto dma = [&](int w0, int st) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t m0v =
+                __builtin_amdgcn_readfirstlane(lds0 + 4u * (uint32_t)(st * STAGE) + 1024u * (uint32_t)(wave + 8 * j));
+            asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v),
+                         "v"(dsrc[j] + w0)
+                         : "memory");
+        }
+    };
     auto stream = [&](int w_lo, int w_hi, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
         const int n = (w_hi - w_lo) / BKW;
         if (n == 0) return;
+        if constexpr (kBigDma) {
+            dma(w_lo, 0);
+            if (n > 1) dma(w_lo + BKW, 1);
+            for (int c = 0; c < n; ++c) {
+                // this wave's loads of chunk c are done once at most the four of chunk c + 1 are out
+                if (c + 1 < n)
+                    asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+                else
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();  // every wave's chunk c is in LDS, every wave is done with chunk c - 1
+                if (c + 2 < n) dma(w_lo + (c + 2) * BKW, (c + 2) % 3);
+                chunk(c % 3, re, im);
+            }
+            __syncthreads();  // the stages are refilled from stage 0 by the next stream / the epilogue
+            return;
+        }
         auto at = [&](int c) { return w_lo + min(c, n - 1) * BKW; };
         gload(ra, at(0));
         gload(rb, at(1));
