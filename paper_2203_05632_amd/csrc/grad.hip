@@ -15,6 +15,8 @@
 // with the PyTorch convention dV/dRe + i dV/dIm for complex gradients.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace {
@@ -53,6 +55,8 @@ __device__ inline bool grad_item(int n_rt, int n_ct, int &rt, int &ct) {
 __device__ inline double2 to_d2(const double2 &v) { return v; }
 __device__ inline double2 to_d2(const float2 &v) { return double2{(double)v.x, (double)v.y}; }
 
+typedef float f2v __attribute__((ext_vector_type(2)));
+
 // P: element type of psi (double2 in FP64 mode, float2 in the low-precision modes)
 template <int NT, typename P>
 __global__ __launch_bounds__(256) void grad_gemm_kernel(
@@ -88,7 +92,16 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
     const int e0 = tid, e1 = tid + 256;
     // staging registers as ext_vector_type (HIP's double2 struct would be kept in scratch memory)
     typedef double d2v __attribute__((ext_vector_type(2)));
-    d2v ra[NT][2], rb[2];
+    // FP32 psi: rows past k_hi are loaded clamped (always in bounds) and zeroed
+    // when staged, so the load is unconditional and its wait (with the FP32 ->
+    // FP64 conversion) falls at the LDS store after the chunk's MFMAs; loaded
+    // under a condition, the conversion's wait sat right behind the chunk's
+    // loads and drained the prefetch.  FP64 psi keeps the conditional load
+    // (measured slightly faster there).
+    constexpr bool F32 = std::is_same<P, float2>::value;
+    using PV = typename std::conditional<F32, f2v, d2v>::type;
+    d2v ra[NT][2];
+    PV rb[2];
     auto gload = [&](int y0) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -96,9 +109,13 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
 #pragma unroll
             for (int t = 0; t < NT; ++t)
                 ra[t][j] = *reinterpret_cast<const d2v *>(&H[(size_t)(t0 + t) * RR + (size_t)(x0 + r) * R + y]);
-            const int kk = k0 + r;
-            const double2 pv = kk < k_hi ? to_d2(psi[(size_t)kk * R + y]) : double2{0.0, 0.0};
-            rb[j] = d2v{pv.x, pv.y};
+            if constexpr (F32) {
+                rb[j] = *reinterpret_cast<const PV *>(&psi[(size_t)min(k0 + r, k_hi - 1) * R + y]);
+            } else {
+                const int kk = k0 + r;
+                const double2 pv = kk < k_hi ? psi[(size_t)kk * R + y] : double2{0.0, 0.0};
+                rb[j] = d2v{pv.x, pv.y};
+            }
         }
     };
     auto lstore = [&](int buf) __attribute__((always_inline)) {
@@ -107,7 +124,11 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(
             const int e = j ? e1 : e0, r = e >> 4, y = e & 15;
 #pragma unroll
             for (int t = 0; t < NT; ++t) *reinterpret_cast<d2v *>(&pa[buf][t][y][r]) = ra[t][j];
-            *reinterpret_cast<d2v *>(&pb[buf][y][r]) = rb[j];
+            if constexpr (F32)
+                *reinterpret_cast<d2v *>(&pb[buf][y][r]) =
+                    k0 + r < k_hi ? d2v{(double)rb[j].x, (double)rb[j].y} : d2v{0.0, 0.0};
+            else
+                *reinterpret_cast<d2v *>(&pb[buf][y][r]) = rb[j];
         }
     };
 
