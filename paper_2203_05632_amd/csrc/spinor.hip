@@ -207,40 +207,40 @@ __global__ __launch_bounds__(256) void spinor_tile_kernel(const double *__restri
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
 
     d2v ra[PA], rb[PB];
-    // Loads are branch-free: indices past the end read the last valid element;
-    // primitives past the set's end are zeroed (they must not contribute).
+    // Loads are branch-free: indices past the end read the last valid element.
+    // Primitives past the set's end are zeroed (they must not contribute) when
+    // the chunk is staged, so the loads' wait falls at the LDS store, after the
+    // current chunk's MFMAs (a select at load time made the compiler wait for
+    // the whole prefetch before them).
     auto gload = [&](int mu0) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < PA; ++j) {
             const int u = min(tid + 256 * j, NAU - 1);
             const int ml = u / (2 * KS), sp = (u / KS) & 1, k = u % KS;
-            const int mu = mu0 + ml;
-            const d2v v = *reinterpret_cast<const d2v *>(
-                coef + 2 * (((size_t)sp * nb + min(mu, mu_hi - 1)) * nsp + min(k0 + k, nsp - 1)));
-            ra[j] = mu < mu_hi ? v : d2v{0.0, 0.0};
+            ra[j] = *reinterpret_cast<const d2v *>(
+                coef + 2 * (((size_t)sp * nb + min(mu0 + ml, mu_hi - 1)) * nsp + min(k0 + k, nsp - 1)));
         }
 #pragma unroll
         for (int j = 0; j < PB; ++j) {
             const int u = min(tid + 256 * j, NBU - 1);
             const int ml = u / (PTS / 2), p2 = u % (PTS / 2);
-            const int mu = mu0 + ml;
-            const d2v v = *reinterpret_cast<const d2v *>(XT + (size_t)min(mu, mu_hi - 1) * E +
-                                                         min(pt0 + 2 * p2, E - 2));
-            rb[j] = mu < mu_hi ? v : d2v{0.0, 0.0};
+            rb[j] = *reinterpret_cast<const d2v *>(XT + (size_t)min(mu0 + ml, mu_hi - 1) * E +
+                                                   min(pt0 + 2 * p2, E - 2));
         }
     };
-    auto lstore = [&](int buf) __attribute__((always_inline)) {
+    auto lstore = [&](int buf, int mu0) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < PA; ++j) {
             const int u = min(tid + 256 * j, NAU - 1);
             const int ml = u / (2 * KS), sp = (u / KS) & 1, k = u % KS;
-            *reinterpret_cast<d2v *>(&As[buf][ml * AROW + 4 * k + 2 * sp]) = ra[j];
+            *reinterpret_cast<d2v *>(&As[buf][ml * AROW + 4 * k + 2 * sp]) =
+                mu0 + ml < mu_hi ? ra[j] : d2v{0.0, 0.0};
         }
 #pragma unroll
         for (int j = 0; j < PB; ++j) {
             const int u = min(tid + 256 * j, NBU - 1);
             const int ml = u / (PTS / 2), p2 = u % (PTS / 2);
-            *reinterpret_cast<d2v *>(&Bs[buf][ml * BROW + 2 * p2]) = rb[j];
+            *reinterpret_cast<d2v *>(&Bs[buf][ml * BROW + 2 * p2]) = mu0 + ml < mu_hi ? rb[j] : d2v{0.0, 0.0};
         }
     };
     acc_t acc[WR][WP];
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void spinor_tile_kernel(const double *__restri
 
     const int n_chunks = (mu_hi - mu_lo + KC - 1) / KC;
     gload(mu_lo);
-    lstore(0);
+    lstore(0, mu_lo);
     __syncthreads();
     for (int c = 0; c < n_chunks; ++c) {
         const int buf = c & 1;
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void spinor_tile_kernel(const double *__restri
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bv[j], acc[i][j], 0, 0, 0);
                 }
         }
-        if (c + 1 < n_chunks) lstore(buf ^ 1);
+        if (c + 1 < n_chunks) lstore(buf ^ 1, mu_lo + KC * (c + 1));
         __syncthreads();
     }
 
