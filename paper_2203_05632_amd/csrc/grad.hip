@@ -365,22 +365,39 @@ __global__ __launch_bounds__(256) void coef_grad_tile_kernel(const double *__res
         for (int j = 0; j < 2; ++j) {
             const int k = k0 + 32 * wk + 16 * j + li;
             if (k >= nsp) continue;
+            if (sum) {
+                // the four elements' running sums are all loaded before any is updated
+                // (loaded one at a time, each load waited for the previous stores)
+                double2 sa[4], ca[4], sb[4], cb[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int mr = mu0 + 32 * wm + 16 * i + 4 * v + lk;
-                if (mr >= mu_hi) continue;
-                const size_t ia = (size_t)mr * nsp + k, ib = ((size_t)nb + mr) * nsp + k;  // alpha, beta
-                if (sum) {
-                    double2 sa = sum[ia], ca = comp[ia], sb = sum[ib], cb = comp[ib];
-                    neumaier(sa.x, ca.x, acc[i][j][0][v]);
-                    neumaier(sa.y, ca.y, acc[i][j][1][v]);
-                    neumaier(sb.x, cb.x, acc[i][j][2][v]);
-                    neumaier(sb.y, cb.y, acc[i][j][3][v]);
-                    sum[ia] = sa;
-                    comp[ia] = ca;
-                    sum[ib] = sb;
-                    comp[ib] = cb;
-                } else {
+                for (int v = 0; v < 4; ++v) {
+                    const int mr = min(mu0 + 32 * wm + 16 * i + 4 * v + lk, mu_hi - 1);
+                    const size_t ia = (size_t)mr * nsp + k, ib = ((size_t)nb + mr) * nsp + k;  // alpha, beta
+                    sa[v] = sum[ia];
+                    ca[v] = comp[ia];
+                    sb[v] = sum[ib];
+                    cb[v] = comp[ib];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int mr = mu0 + 32 * wm + 16 * i + 4 * v + lk;
+                    if (mr >= mu_hi) continue;
+                    const size_t ia = (size_t)mr * nsp + k, ib = ((size_t)nb + mr) * nsp + k;
+                    neumaier(sa[v].x, ca[v].x, acc[i][j][0][v]);
+                    neumaier(sa[v].y, ca[v].y, acc[i][j][1][v]);
+                    neumaier(sb[v].x, cb[v].x, acc[i][j][2][v]);
+                    neumaier(sb[v].y, cb[v].y, acc[i][j][3][v]);
+                    sum[ia] = sa[v];
+                    comp[ia] = ca[v];
+                    sum[ib] = sb[v];
+                    comp[ib] = cb[v];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int mr = mu0 + 32 * wm + 16 * i + 4 * v + lk;
+                    if (mr >= mu_hi) continue;
+                    const size_t ia = (size_t)mr * nsp + k, ib = ((size_t)nb + mr) * nsp + k;  // alpha, beta
                     grad_coeffs[ia] = double2{acc[i][j][0][v], acc[i][j][1][v]};
                     grad_coeffs[ib] = double2{acc[i][j][2][v], acc[i][j][3][v]};
                 }
