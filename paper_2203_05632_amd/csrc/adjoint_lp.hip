@@ -56,11 +56,10 @@ __device__ inline int swz(int row, int unit) { return row * 8 + (unit ^ (row & 7
 // issue order, so a wait the compiler places for its own later loads also
 // covers these.
 // The loads take their LDS address in M0, which the assembly sets without
-// declaring it (M0 is reserved: the compiler neither allocates it nor keeps
-// values in it across such statements); the compiled kernel uses M0 for
-// nothing else, which was checked in its AMD assembly (every M0 write is one
-// of these).  The s_nop covers the wait state an M0 write needs before an LDS
-// DMA reads it.
+// declaring it (the compiler does not allocate M0): this relies on the
+// compiled kernels using M0 for nothing else, which a CPU test checks in
+// their AMD assembly (every M0 access is one of these loads or its set-up).
+// The s_nop covers the wait state an M0 write needs before an LDS DMA reads it.
 template <int WN, int NCW, bool DMA>
 __global__ __launch_bounds__(128 * NCW) void adj_lp_kernel(
     const uint32_t *__restrict__ Hm, const uint32_t *__restrict__ Hp, const uint32_t *__restrict__ V,

@@ -314,11 +314,10 @@ __device__ inline f4v mfma_pair(u32x4 a, u32x4 b, f4v c) {
 // compiler does not track these loads, so it adds no waits of its own before
 // the LDS reads); otherwise by two register stages into two LDS stages.
 // The loads take their LDS address in M0, which the assembly sets without
-// declaring it (M0 is reserved: the compiler neither allocates it nor keeps
-// values in it across such statements); the compiled kernel uses M0 for
-// nothing else, which was checked in its AMD assembly (every M0 write is one
-// of these).  The s_nop covers the wait state an M0 write needs before an LDS
-// DMA reads it.
+// declaring it (the compiler does not allocate M0): this relies on the
+// compiled kernels using M0 for nothing else, which a CPU test checks in
+// their AMD assembly (every M0 access is one of these loads or its set-up).
+// The s_nop covers the wait state an M0 write needs before an LDS DMA reads it.
 constexpr bool kBigDma = true;
 
 template <typename T, bool GRAD>
