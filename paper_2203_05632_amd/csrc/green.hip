@@ -201,7 +201,10 @@ __device__ inline double scale_load(const double *__restrict__ sc, int nsp, int 
 // Stream spinors k in [k_lo, k_hi) through the LDS panels in chunks of KC
 // (the next chunk's global loads are in flight while the current one feeds
 // the MFMAs) and accumulate this wave's sub-tile for NT tau samples.
-template <typename T, int NT>
+// TWO: two register stages of prefetch (used by the gradient kernels, which
+// run at two waves per SIMD with or without the second stage; the forward
+// kernels would lose a wave per SIMD to its registers).
+template <typename T, int NT, bool TWO>
 __device__ inline void stream_k(const typename GOp<T>::V2 *__restrict__ psi, const double *__restrict__ sc, int nsp,
                                 int R, int rp, int rq, int k_lo, int k_hi, typename GOp<T>::V2 (*panel)[2][KC][32],
                                 double (*spanel)[4 * KC], typename GOp<T>::Acc (&t1)[NT],
@@ -216,36 +219,74 @@ __device__ inline void stream_k(const typename GOp<T>::V2 *__restrict__ psi, con
     // (Plain scalars here: a lambda version over register arrays crashes the
     // ROCm 7.2 AMDGPU backend in machine copy propagation.)
     const int e0 = tid, e1 = tid + 256;
-    V2 ra0, ra1, rb0, rb1;
-    double sv;
     const int n_chunks = (k_hi - k_lo + KC - 1) / KC;
-    chunk_load(psi, R, rp, rq, k_lo, k_hi, e0, e1, ra0, ra1, rb0, rb1);
-    sv = scale_load(sc, nsp, NT, k_lo, k_hi, tid);
-    chunk_store(panel[0], e0, e1, ra0, ra1, rb0, rb1);
-    if (tid < 4 * KC) spanel[0][tid] = sv;
-    __syncthreads();
-    for (int c = 0; c < n_chunks; ++c) {
-        const int buf = c & 1;
-        const int kc = k_lo + c * KC;
-        if (c + 1 < n_chunks) {
-            chunk_load(psi, R, rp, rq, kc + KC, k_hi, e0, e1, ra0, ra1, rb0, rb1);
-            sv = scale_load(sc, nsp, NT, kc + KC, k_hi, tid);
-        }
-        // operands of this chunk come from LDS only, so the next chunk's
-        // global loads stay in flight across all of its MFMAs
-#pragma unroll
-        for (int ks = 0; ks < KC; ks += 4) {
-            double s[NT];
-            for (int t = 0; t < NT; ++t) s[t] = spanel[buf][t * KC + ks + lk];
-            mfma_kstep<T, NT>(&panel[buf][0][ks + lk][16 * wp + li], &panel[buf][1][ks + lk][16 * wq + li], s, t1,
-                              t2, t3);
-        }
-        if (c + 1 < n_chunks) {
-            chunk_store(panel[buf ^ 1], e0, e1, ra0, ra1, rb0, rb1);
-            if (tid < 4 * KC) spanel[buf ^ 1][tid] = sv;
-        }
-        __syncthreads();
+#define GK_COMPUTE(BUF)                                                                                             \
+    _Pragma("unroll") for (int ks = 0; ks < KC; ks += 4) {                                                          \
+        double s[NT];                                                                                               \
+        for (int t = 0; t < NT; ++t) s[t] = spanel[BUF][t * KC + ks + lk];                                          \
+        mfma_kstep<T, NT>(&panel[BUF][0][ks + lk][16 * wp + li], &panel[BUF][1][ks + lk][16 * wq + li], s, t1, t2, t3); \
     }
+    if constexpr (TWO) {
+        // Two register stages: the loads of chunk c + 2 are issued before chunk
+        // c is multiplied and go to LDS after chunk c + 1 is; past the last
+        // chunk the loads re-read it (branch-free, so the compiler's waits at
+        // each LDS store cover only the older stage).
+        V2 ra0, ra1, rb0, rb1, qa0, qa1, qb0, qb1;
+        double sv, sw;
+        const int k_last = k_lo + (n_chunks - 1) * KC;
+        chunk_load(psi, R, rp, rq, k_lo, k_hi, e0, e1, ra0, ra1, rb0, rb1);
+        sv = scale_load(sc, nsp, NT, k_lo, k_hi, tid);
+        chunk_load(psi, R, rp, rq, min(k_lo + KC, k_last), k_hi, e0, e1, qa0, qa1, qb0, qb1);
+        sw = scale_load(sc, nsp, NT, min(k_lo + KC, k_last), k_hi, tid);
+        chunk_store(panel[0], e0, e1, ra0, ra1, rb0, rb1);
+        if (tid < 4 * KC) spanel[0][tid] = sv;
+        __syncthreads();
+        for (int c = 0; c < n_chunks; c += 2) {
+            const int k2 = min(k_lo + (c + 2) * KC, k_last), k3 = min(k_lo + (c + 3) * KC, k_last);
+            chunk_load(psi, R, rp, rq, k2, k_hi, e0, e1, ra0, ra1, rb0, rb1);  // (q) holds chunk c + 1
+            sv = scale_load(sc, nsp, NT, k2, k_hi, tid);
+            GK_COMPUTE(0)
+            if (c + 1 < n_chunks) {
+                chunk_store(panel[1], e0, e1, qa0, qa1, qb0, qb1);
+                if (tid < 4 * KC) spanel[1][tid] = sw;
+            }
+            __syncthreads();
+            if (c + 1 >= n_chunks) break;
+            chunk_load(psi, R, rp, rq, k3, k_hi, e0, e1, qa0, qa1, qb0, qb1);  // (r) holds chunk c + 2
+            sw = scale_load(sc, nsp, NT, k3, k_hi, tid);
+            GK_COMPUTE(1)
+            if (c + 2 < n_chunks) {
+                chunk_store(panel[0], e0, e1, ra0, ra1, rb0, rb1);
+                if (tid < 4 * KC) spanel[0][tid] = sv;
+            }
+            __syncthreads();
+        }
+    } else {
+        V2 ra0, ra1, rb0, rb1;
+        double sv;
+        chunk_load(psi, R, rp, rq, k_lo, k_hi, e0, e1, ra0, ra1, rb0, rb1);
+        sv = scale_load(sc, nsp, NT, k_lo, k_hi, tid);
+        chunk_store(panel[0], e0, e1, ra0, ra1, rb0, rb1);
+        if (tid < 4 * KC) spanel[0][tid] = sv;
+        __syncthreads();
+        for (int c = 0; c < n_chunks; ++c) {
+            const int buf = c & 1;
+            const int kc = k_lo + c * KC;
+            if (c + 1 < n_chunks) {
+                chunk_load(psi, R, rp, rq, kc + KC, k_hi, e0, e1, ra0, ra1, rb0, rb1);
+                sv = scale_load(sc, nsp, NT, kc + KC, k_hi, tid);
+            }
+            // operands of this chunk come from LDS only, so the next chunk's
+            // global loads stay in flight across all of its MFMAs
+            GK_COMPUTE(buf)
+            if (c + 1 < n_chunks) {
+                chunk_store(panel[buf ^ 1], e0, e1, ra0, ra1, rb0, rb1);
+                if (tid < 4 * KC) spanel[buf ^ 1][tid] = sv;
+            }
+            __syncthreads();
+        }
+    }
+#undef GK_COMPUTE
 }
 
 // G entry v of a lane's accumulators from the GEMM's partial sums
@@ -309,7 +350,7 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
     {
         Acc m1[NT], m2[NT], m3[NT];
         for (int t = 0; t < NT; ++t) m1[t] = m2[t] = m3[t] = Acc{0, 0, 0, 0};
-        stream_k<T, NT>(psi, sc, nsp, R, rp, rq, 0, no, panel, spanel, m1, m2, m3);
+        stream_k<T, NT, GRAD && !BREIT>(psi, sc, nsp, R, rp, rq, 0, no, panel, spanel, m1, m2, m3);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -317,7 +358,7 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
     }
     Acc p1[NT], p2[NT], p3[NT];
     for (int t = 0; t < NT; ++t) p1[t] = p2[t] = p3[t] = Acc{0, 0, 0, 0};
-    stream_k<T, NT>(psi, sc, nsp, R, rp, rq, no, nsp, panel, spanel, p1, p2, p3);
+    stream_k<T, NT, GRAD && !BREIT>(psi, sc, nsp, R, rp, rq, no, nsp, panel, spanel, p1, p2, p3);
 
     // epilogue: per tau, stage the wave's G- and G+ sub-tiles in LDS and contract
     cplx *Gm = reinterpret_cast<cplx *>(smem) + wave * 512;
