@@ -53,7 +53,7 @@ VARIANTS = {
     "C3": [("fp64", False), ("fp32", True), ("bf16", False), ("bf16", True), ("fp16", True)],
     "C1": [("fp64", False), ("fp32", False), ("bf16", False), ("fp16", False), ("bf16", True), ("fp16", True),
            ("fp64", False, "gaunt"), ("fp64", False, "breit"), ("bf16", False, "breit"),
-           ("fp64", True, "breit")],
+           ("fp64", True, "breit"), ("bf16", True, "breit")],
     "C0": [("fp64", False), ("bf16", True)],
 }
 STAT_PRECISIONS = ["fp32", "bf16", "fp16"]   # replayed with gradients against the FP64 replay

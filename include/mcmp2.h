@@ -126,8 +126,7 @@ int mcmp2_init(const mcmp2_basis *basis, const double *coeffs, const double *eps
  *   Gradients overwrite their outputs.  Either requires want_grad at init
  *   (ESTATE otherwise); they come from a hand-written adjoint of the same
  *   step (Green's-function blocks recomputed, not stored between calls).
- * Errors: EINVAL (null pointers, n_tau out of range, gradient outputs with a
- * non-Coulomb interaction in the BF16 / FP16 modes), ESTATE, EDEVICE.
+ * Errors: EINVAL (null pointers, n_tau out of range), ESTATE, EDEVICE.
  */
 int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
                double *value, double *grad_eps, double *grad_coeffs);
@@ -146,9 +145,8 @@ int mcmp2_step(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t
  *                             grad_coeffs), 16-byte aligned.
  * The caller zeroes the pairs to start; the running total of a gradient is
  * sum + comp.
- * Errors: EINVAL (null pointers, n_tau out of range, a non-Coulomb
- * interaction in the BF16 / FP16 modes), ESTATE (context without want_grad),
- * EDEVICE.
+ * Errors: EINVAL (null pointers, n_tau out of range), ESTATE (context without
+ * want_grad), EDEVICE.
  */
 int mcmp2_step_accumulate(mcmp2_ctx *ctx, const double *walkers, const double *tau, int32_t n_tau, double *e2_out,
                           double *eps_sum, double *eps_comp, double *coeffs_sum, double *coeffs_comp);
@@ -181,13 +179,11 @@ int mcmp2_set_coefficients(mcmp2_ctx *ctx, const double *coeffs, const double *e
  * estimator).  The Gaunt and Breit terms are evaluated in every precision
  * mode, the alpha-weighted contraction in FP64 on the mode's Green's
  * functions (in the BF16 / FP16 modes through the 32 x 32-tile Green's
- * kernel at every size).  Gradient outputs are available with them in the
- * FP64 and FP32 modes: the adjoint of the alpha-weighted contraction is
- * formed in FP64 beside it, and the adjoint GEMMs are those of the Coulomb
- * interaction.
- * Errors: EINVAL (null context, unknown kind).  mcmp2_step and
- * mcmp2_step_accumulate return EINVAL when gradient outputs are requested
- * with a non-Coulomb interaction in the BF16 / FP16 modes.
+ * kernel at every size).  Gradient outputs are available with them in every
+ * mode: the adjoint of the alpha-weighted contraction is formed in FP64 from
+ * the pairs' Green's-function blocks (kept as BF16 pairs in the BF16 / FP16
+ * modes), and the adjoint GEMMs are those of the Coulomb interaction.
+ * Errors: EINVAL (null context, unknown kind).
  */
 int mcmp2_set_interaction(mcmp2_ctx *ctx, int32_t interaction);
 

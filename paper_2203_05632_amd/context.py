@@ -161,8 +161,7 @@ class Context:
 
     def set_interaction(self, kind: str) -> None:
         """Electron-electron interaction of the following steps: "coulomb"
-        (default), "gaunt" or "breit" (any precision; gradients in the FP64 and
-        FP32 modes)."""
+        (default), "gaunt" or "breit" (any precision, with or without gradients)."""
         check(self._lib.mcmp2_set_interaction(self._h, INTERACTIONS[kind]))
 
     def pair_weights(self, walkers: torch.Tensor, w: torch.Tensor) -> torch.Tensor:

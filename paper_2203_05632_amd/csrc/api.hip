@@ -373,10 +373,6 @@ static int run_step(mcmp2_ctx *c, const double *walkers, const double *tau, int3
         set_error("gradient outputs requested but the context was created with want_grad = 0");
         return MCMP2_ESTATE;
     }
-    if (grad && c->interaction != MCMP2_COULOMB && c->precision != MCMP2_FP64 && c->precision != MCMP2_FP32) {
-        set_error("gradients with the Gaunt / Breit interaction are available in the FP64 and FP32 modes only");
-        return MCMP2_EINVAL;
-    }
     int rc;
     if ((rc = timed(c, MCMP2_K_STEP_PREP, "step_prep", [&] { return launch_step_prep(c, walkers, tau, n_tau); })) !=
         MCMP2_OK)

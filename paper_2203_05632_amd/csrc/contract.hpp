@@ -476,10 +476,12 @@ __device__ inline cplx breit_xblock(FL L, FM M, FR Rm, int l16, const double (&b
 //   X2 = sum s_nu P23 [sum B12[mu nu] B34[rho sig] s_rho A13^H s_mu] P14 s_sig,
 //   X3 = sum s_mu A13 [sum B12[mu nu] B34[rho sig] s_rho P23^H s_nu] A24 s_sig,
 //   X4 = sum s_nu A24 [sum B12[mu nu] B34[rho sig] s_sig P14^H s_mu] A13 s_rho.
+// HT: double2 (FP64 blocks) or uint32_t (BF16 pairs, rounded once from FP64).
+template <typename HT>
 __device__ inline void breit_adjoint_pair(const cplx *Gm, const cplx *Gp, int ld, int p, int q, bool ok,
                                           const double *__restrict__ hinv, const double *__restrict__ rhat, double c,
-                                          double wt, double cgrad, int R, double2 *__restrict__ Hm,
-                                          double2 *__restrict__ Hp) {
+                                          double wt, double cgrad, int R, HT *__restrict__ Hm,
+                                          HT *__restrict__ Hp) {
     if (!ok) return;  // ok is the same in all 16 lanes of the pair
     const int lane = threadIdx.x & 63, l16 = lane & 15, grp = lane & ~15;
     const int a = l16 >> 2, b = l16 & 3;
@@ -520,9 +522,9 @@ __device__ inline void breit_adjoint_pair(const cplx *Gm, const cplx *Gp, int ld
             h24p = cadd(h24p, cmul(conjc(Vm), qrot(GB(Gm, 1, 1, r, cc), qp)));
         }
     const size_t r1 = 8 * p + a, r2 = 8 * p + 4 + a, c3 = 8 * q + b, c4 = 8 * q + 4 + b;
-    auto put = [&](double2 *H, size_t r, size_t cc, cplx v, double scale) {  // and the Hermitian partner
-        H[r * R + cc] = double2{v.re * scale, v.im * scale};
-        H[cc * R + r] = double2{v.re * scale, -v.im * scale};
+    auto put = [&](HT *H, size_t r, size_t cc, cplx v, double scale) {  // and the Hermitian partner
+        h_store(H, r * R + cc, v.re * scale, v.im * scale);
+        h_store(H, cc * R + r, v.re * scale, -v.im * scale);
     };
     put(Hp, r1, c3, h13p, cw);
     put(Hp, r2, c4, h24p, cw);

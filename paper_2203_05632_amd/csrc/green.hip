@@ -37,6 +37,8 @@
 // slices fit that XCD's L2 (build_green_work).
 #include <algorithm>
 
+#include <type_traits>
+
 #include "contract.hpp"
 
 namespace {
@@ -407,8 +409,11 @@ green_contract_kernel(const void *__restrict__ psi_, const double *__restrict__ 
 // kernel); each pair reads its own blocks and overwrites those with its
 // adjoint blocks, writing their Hermitian partners into the (q, p) blocks,
 // which no pair reads.  Diagonal and padding blocks are never written.
+// HT: double2 (FP64, FP32 modes) or uint32_t (BF16 pairs: BF16 / FP16 modes,
+// G read as BF16 pairs, the adjoint formed in FP64 and rounded once).
+template <typename HT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void
-breit_adjoint_kernel(double2 *__restrict__ Hm, double2 *__restrict__ Hp, const double *__restrict__ wtau,
+breit_adjoint_kernel(HT *__restrict__ Hm, HT *__restrict__ Hp, const double *__restrict__ wtau,
                      const double *__restrict__ hinv, const int *__restrict__ tiles, const int *__restrict__ work,
                      int R, int m, double cgrad, const double *__restrict__ rhat, double gauge) {
     __shared__ __align__(16) cplx sg[4][2][256];
@@ -419,17 +424,23 @@ breit_adjoint_kernel(double2 *__restrict__ Hm, double2 *__restrict__ Hp, const d
     const int PT = tiles[2 * item], QT = tiles[2 * item + 1];
     const int p0 = kTileWalkers * PT + 2 * wp, q0 = kTileWalkers * QT + 2 * wq;
     if (p0 >= q0 + 1 || q0 >= m) return;  // no pair p < q < m in this wave's sub-tile
-    double2 *hm = Hm + (size_t)t * R * R, *hp = Hp + (size_t)t * R * R;
+    HT *hm = Hm + (size_t)t * R * R, *hp = Hp + (size_t)t * R * R;
     cplx *Gm = sg[wave][0], *Gp = sg[wave][1];
     const int li = lane & 15, lk = lane >> 4;
     const size_t r0 = 8 * (size_t)p0, c0 = 8 * (size_t)q0;
+    auto wide = [](HT x) {
+        if constexpr (std::is_same_v<HT, uint32_t>)  // BF16 pair, real part low
+            return cplx{(double)__uint_as_float(x << 16), (double)__uint_as_float(x & 0xffff0000u)};
+        else
+            return cplx{x.x, x.y};
+    };
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 4 * v + lk;
         const size_t o = (r0 + i) * R + c0 + li;
-        const double2 x = hm[o], y = hp[o];
-        Gm[i * 16 + li] = cplx{x.x, x.y};
-        Gp[i * 16 + li] = cplx{y.x, y.y};
+        const HT x = hm[o], y = hp[o];
+        Gm[i * 16 + li] = wide(x);
+        Gp[i * 16 + li] = wide(y);
     }
     // the sub-tiles are private to the wave, whose LDS accesses complete in order
     __builtin_amdgcn_wave_barrier();
@@ -541,8 +552,8 @@ void launch_green_dispatch(const mcmp2_ctx *c, dim3 grid, bool grad, bool breit,
             green_contract_kernel<T, 1, true, true><<<grid, 256, 0, c->stream>>>(
                 c->psi, c->scale, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->no, c->nsp, c->m,
                 c->partial, Hm, Hp, cgrad, c->rhat, gauge);
-            breit_adjoint_kernel<<<grid, 256, 0, c->stream>>>(Hm, Hp, c->wtau, c->hinv, c->tiles, c->work, c->R, c->m,
-                                                               cgrad, c->rhat, gauge);
+            breit_adjoint_kernel<double2><<<grid, 256, 0, c->stream>>>(Hm, Hp, c->wtau, c->hinv, c->tiles, c->work,
+                                                                        c->R, c->m, cgrad, c->rhat, gauge);
             return;
         }
     }
@@ -600,6 +611,16 @@ hipError_t launch_green_contract(const mcmp2_ctx *c, int n_tau, bool grad) {
     return hipGetLastError();
 }
 
+
+// BF16 / FP16 modes: the Gaunt / Breit adjoint on the G blocks the 32 x 32-tile
+// Green's kernel left in Hm / Hp (BF16 pairs), grid as that kernel's.
+hipError_t launch_breit_adjoint_lp(const mcmp2_ctx *c, int n_tau, double cgrad) {
+    const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
+    breit_adjoint_kernel<uint32_t><<<dim3(c->n_slots / 4, n_tau), 256, 0, c->stream>>>(
+        reinterpret_cast<uint32_t *>(c->Hm), reinterpret_cast<uint32_t *>(c->Hp), c->wtau, c->hinv, c->tiles, c->work,
+        c->R, c->m, cgrad, c->rhat, gauge);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce(const mcmp2_ctx *c, int n_tau, double *e2_out) {
     const double inv_pairs = 1.0 / (0.5 * (double)c->m * (double)(c->m - 1));

@@ -220,10 +220,12 @@ __device__ __attribute__((always_inline)) inline void lp_stream(const T *__restr
 
 // HT: element type of the adjoint blocks (FP64 complex with FP32 operands,
 // packed BF16 pairs with BF16 / FP16 operands).  BREIT: the Gaunt / Breit
-// interaction (one tau per block, no gradients): the FP32 Green's functions
-// are staged in FP64 and go through the FP64 alpha-weighted contraction of
-// the FP64 / FP32 modes (contract_pairs_breit; rhat [m_pad][4] unit vectors of
-// r1p - r2p, gauge = weight of the second Breit term).
+// interaction (one tau per block): the FP32 Green's functions are staged in
+// FP64 and go through the FP64 alpha-weighted contraction of the FP64 / FP32
+// modes (contract_pairs_breit; rhat [m_pad][4] unit vectors of r1p - r2p,
+// gauge = weight of the second Breit term); with GRAD the kernel copies the
+// pairs' G blocks into Hm / Hp as BF16 pairs for the Breit adjoint kernel
+// (G-(1,3), G-(2,4) and the four G+ blocks of each pair p < q < m).
 template <typename T, int NT, bool GRAD, typename HT, bool BREIT = false>
 __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, int Ko, int Ktot,
                                                        const double *__restrict__ wtau, const double *__restrict__ hinv,
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
                                                        double *__restrict__ partial, HT *__restrict__ Hm,
                                                        HT *__restrict__ Hp, double cgrad,
                                                        const double *__restrict__ rhat = nullptr, double gauge = 0.0) {
-    static_assert(!BREIT || (NT == 1 && !GRAD), "the Gaunt / Breit contraction takes one tau and no gradients");
+    static_assert(!BREIT || NT == 1, "the Gaunt / Breit contraction takes one tau");
     const int t0 = t_base + (int)blockIdx.y * NT;  // tau samples t0 .. t0 + NT - 1
     constexpr int PANEL_BYTES = 2 * NT * 2 * 32 * lrow<T>() * (int)sizeof(T);
     constexpr int EPI_BYTES = 4 * 512 * (int)sizeof(cplx);
@@ -265,6 +267,16 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
             const int i = 4 * lk + v;  // MFMA f32 result row of element v
             Gm[i * 16 + li] = {(double)gm_re[t][v], (double)gm_im[t][v]};
             Gp[i * 16 + li] = {(double)gp_re[t][v], (double)gp_im[t][v]};
+            if constexpr (GRAD && BREIT) {
+                // the pair blocks p < q < m for the Breit adjoint kernel, as BF16 pairs:
+                // G- only in its (1,3), (2,4) blocks (H-(1,4), H-(2,3) stay zero), all of G+
+                const int row = rp + 16 * (wave >> 1) + i, col = rq + 16 * (wave & 1) + li;
+                if ((row >> 3) < (col >> 3) && (col >> 3) < m) {
+                    const size_t o = (size_t)(t0 + t) * R * R + (size_t)row * R + col;
+                    if (((row ^ col) & 4) == 0) Hm[o] = bf16_pair(gm_re[t][v], gm_im[t][v]);
+                    Hp[o] = bf16_pair(gp_re[t][v], gp_im[t][v]);
+                }
+            }
         }
         // wave-private staging (the K loop ended with a block barrier); one
         // wave's LDS accesses complete in order
@@ -524,13 +536,21 @@ hipError_t launch_lp_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     uint32_t *Hm = reinterpret_cast<uint32_t *>(c->Hm), *Hp = reinterpret_cast<uint32_t *>(c->Hp);
     const int nblocks = c->n_slots / 4;
-    if (c->interaction != MCMP2_COULOMB) {  // no gradients: the step rejects them in these modes
+    if (c->interaction != MCMP2_COULOMB) {
+        // with gradients: the forward contraction copies the pairs' G blocks into
+        // Hm / Hp, then the Breit adjoint kernel overwrites them with the adjoint
         const double gauge = c->interaction == MCMP2_BREIT ? 1.0 : 0.0;
         const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
-        green_lp_kernel<T, 1, false, uint32_t, true><<<dim3(nblocks, n_tau), 256, 0, c->stream>>>(
-            U, c->Ko, c->Ktot, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->m, 0, c->partial, nullptr,
-            nullptr, 0.0, c->rhat, gauge);
+        if (grad)
+            green_lp_kernel<T, 1, true, uint32_t, true><<<dim3(nblocks, n_tau), 256, 0, c->stream>>>(
+                U, c->Ko, c->Ktot, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->m, 0, c->partial, Hm, Hp,
+                cgrad, c->rhat, gauge);
+        else
+            green_lp_kernel<T, 1, false, uint32_t, true><<<dim3(nblocks, n_tau), 256, 0, c->stream>>>(
+                U, c->Ko, c->Ktot, c->wtau, c->hinv, c->tiles, c->work, c->n_slots, c->R, c->m, 0, c->partial, nullptr,
+                nullptr, 0.0, c->rhat, gauge);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (grad && (e = launch_breit_adjoint_lp(c, n_tau, cgrad)) != hipSuccess) return e;
         return prof_end(c, ps, MCMP2_K_GREEN_GEMM);
     }
     constexpr int NTMAX = 4;

@@ -237,6 +237,8 @@ hipError_t launch_accumulate(const mcmp2_ctx *c, const double *src, double *sum,
 hipError_t launch_adjoint(const mcmp2_ctx *c, const double *tau, int n_tau, grad_out grad_eps);
 hipError_t launch_coef_grad(const mcmp2_ctx *c, grad_out grad_coeffs);
 hipError_t launch_adjoint_lp(const mcmp2_ctx *c, const double *tau, int n_tau);
+// Gaunt / Breit adjoint blocks in the BF16 / FP16 modes (green.hip)
+hipError_t launch_breit_adjoint_lp(const mcmp2_ctx *c, int n_tau, double cgrad);
 hipError_t launch_coef_lp(const mcmp2_ctx *c);
 hipError_t launch_spinor_lp(const mcmp2_ctx *c);
 // true when the split-BF16 spinor GEMM has at least one 128x128 tile per two CUs

@@ -196,18 +196,40 @@ def test_breit_fp32_gradients_near_fp64(kind):
     assert e_err < 1e-5 and c_err < 1e-5
 
 
-def test_breit_gradients_rejected_in_bf16_fp16():
-    from paper_2203_05632_amd._lib import MCMP2Error
-    inp = make_inputs("C0")
-    wk = dev(initial_walkers(inp))
-    for prec in ("bf16", "fp16"):
-        ctx = _ctx(inp, want_grad=True, precision=prec)
-        ctx.set_interaction("gaunt")
-        e2 = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
-        ge = torch.zeros(inp.n_sp, dtype=torch.float64, device="cuda")
-        with pytest.raises(MCMP2Error, match="FP64 and FP32"):
-            ctx.step(wk, dev([0.3]), e2, grad_eps=ge)
-        ctx.step(wk, dev([0.3]), e2)  # forward only is fine
+# Max-norm deviation of the 16-bit Breit / Gaunt gradients from the FP64 mode's:
+# measured up to 1.06e-2 (C1, coefficient gradient; the Coulomb 16-bit
+# gradients there: 5.1e-3); the guard is three times that.  The Breit adjoint
+# reads G as BF16 pairs in both modes, so FP16 is no closer than BF16 here.
+LP_GRAD_BOUND = 3e-2
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("kind", ["gaunt", "breit"])
+@pytest.mark.parametrize("name,over,taus", [("C0", dict(m=13, n_occ=6, n_vir=10, n_tau=3), [0.2, 0.7, 2.5]),
+                                            ("C1", {}, [0.17, 0.83])])
+def test_breit_low_precision_gradients_near_fp64(prec, kind, name, over, taus):
+    """BF16 / FP16 modes: the 32 x 32-tile Green's kernel copies the pairs' G
+    blocks as BF16 pairs, the Breit adjoint kernel forms the adjoint blocks in
+    FP64 and rounds them to BF16, then the 16-bit adjoint GEMM and coefficient
+    gradient run as for the Coulomb interaction.  Against the FP64 mode's
+    Breit gradients (themselves within 1e-9 of the oracle) on the same walkers
+    and tau, in the max norm; the Coulomb interaction's 16-bit gradient error
+    on the same case is printed beside it."""
+    inp = make_inputs(name, **over)
+    wk = initial_walkers(inp)
+    taus = np.array(taus)
+    out = {}
+    for p, k in ((prec, kind), ("fp64", kind), (prec, "coulomb"), ("fp64", "coulomb")):
+        ctx = _ctx(inp, want_grad=True, precision=p, n_tau_max=len(taus))
+        ctx.set_interaction(k)
+        out[p, k] = _gpu_grad(ctx, inp, wk, taus)
+    e_err = _normrel(out[prec, kind][1], out["fp64", kind][1])
+    c_err = _normrel(out[prec, kind][2], out["fp64", kind][2])
+    e_ref = _normrel(out[prec, "coulomb"][1], out["fp64", "coulomb"][1])
+    c_ref = _normrel(out[prec, "coulomb"][2], out["fp64", "coulomb"][2])
+    print(f"{prec} {kind} {name}: eps err {e_err:.2e} coef err {c_err:.2e} "
+          f"(coulomb {prec}: eps {e_ref:.2e} coef {c_ref:.2e})", flush=True)
+    assert e_err < LP_GRAD_BOUND and c_err < LP_GRAD_BOUND
 
 
 def test_breit_gradients_switching_interactions_bitwise():

@@ -219,6 +219,7 @@ def test_step_accumulate_errors():
         Context.from_inputs(inp).step_accumulate(wk, taus, e2, *acc)      # no want_grad
     assert ei.value.code == -4
     ctx = _ctx(inp, precision="bf16")
-    ctx.set_interaction("breit")
-    with pytest.raises(MCMP2Error, match="FP64 and FP32"):
-        ctx.step_accumulate(wk, taus, e2, *acc)
+    ctx.set_interaction("breit")  # gradients with the Breit interaction in every mode
+    ctx.step_accumulate(wk, taus, e2, *acc)
+    torch.cuda.synchronize()
+    assert float(acc[2].abs().max()) > 0
