@@ -6,9 +6,10 @@ kernels with two tau per block and the LDS-tiled spinor GEMM, the BF16 / FP16
 Breit contraction, each against the FP64 oracle on the same walkers and tau.
 
 Gradients at this size are checked through properties that hold at any size:
-the FP64 gradients against central finite differences of the (oracle-pinned)
-FP64 forward step along random directions, with walkers and tau fixed and
-lambda frozen; the BF16 gradients against the FP64 ones.
+the FP64 gradients (Coulomb and Breit interaction) against central finite
+differences of the (oracle-pinned) FP64 forward step along random directions,
+with walkers and tau fixed and lambda frozen; the BF16 gradients against the
+FP64 ones.
 """
 import numpy as np
 import pytest
@@ -84,9 +85,11 @@ def _value(ctx, wk, taus):
     return float(_step(ctx, wk, taus)[:, 2].mean())
 
 
-def test_full_size_fp64_gradients_match_finite_differences(c4):
+@pytest.mark.parametrize("kind", ["coulomb", "breit"])
+def test_full_size_fp64_gradients_match_finite_differences(c4, kind):
     inp, wk, _, _ = c4
     ctx = _ctx(inp, want_grad=True)
+    ctx.set_interaction(kind)
     ge = torch.zeros(inp.n_sp, dtype=torch.float64, device="cuda")
     gc = torch.zeros((2, inp.n_b, inp.n_sp), dtype=torch.complex128, device="cuda")
     _step(ctx, wk, TAUS, grad_eps=ge, grad_coeffs=gc)
@@ -106,7 +109,7 @@ def test_full_size_fp64_gradients_match_finite_differences(c4):
     ctx.set_coefficients(eps=e)
     fd = (vals[0] - vals[1]) / (2 * h)
     an = float(ge @ d)
-    print(f"eps direction: analytic {an:.12e} fd {fd:.12e}", flush=True)
+    print(f"{kind} eps direction: analytic {an:.12e} fd {fd:.12e}", flush=True)
     assert abs(an - fd) <= 1e-6 * float(np.abs(ge) @ np.abs(d))
     # direction in the coefficients
     D = rng.standard_normal(C0.shape) + 1j * rng.standard_normal(C0.shape)
@@ -117,7 +120,7 @@ def test_full_size_fp64_gradients_match_finite_differences(c4):
         vals.append(_value(ctx, wk, TAUS))
     fd = (vals[0] - vals[1]) / (2 * h)
     an = float(np.real(np.vdot(gc, D)))  # Re(conj(g) . D) with g = dV/dRe C + i dV/dIm C
-    print(f"coefficient direction: analytic {an:.12e} fd {fd:.12e}", flush=True)
+    print(f"{kind} coefficient direction: analytic {an:.12e} fd {fd:.12e}", flush=True)
     assert abs(an - fd) <= 1e-6 * float(np.abs(gc).ravel() @ np.abs(D).ravel())
 
 
