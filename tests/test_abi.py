@@ -58,3 +58,11 @@ def test_step_accumulate_validates_before_touching_device():
     assert b"16-byte aligned" in lib.mcmp2_last_error()
     assert lib.mcmp2_step_accumulate(None, p16, p16, 1, p16, p16, p16, p16, p16) == -1
     assert b"null argument" in lib.mcmp2_last_error()
+
+
+def test_headline_traffic_record_matches_sources():
+    """bench.py reports roofline.traffic from the counter record under
+    profiles/ only while the SHA-256 of the kernel's sources matches it; a
+    change to those sources must come with a re-taken record."""
+    import bench
+    assert bench.recorded_traffic("adj_gemm", "C4", "fp64") is not None
