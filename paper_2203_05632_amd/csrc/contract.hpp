@@ -117,10 +117,19 @@ __device__ inline cx<F> to_cx(const float2 &v) {
 // the group and, with GRAD, writes the pair's adjoint blocks and their
 // Hermitian partners into Hm / Hp (R x R, this tau; HT = double2, or
 // uint32_t for BF16 pairs).
-template <bool GRAD, typename HT, typename F, typename GT>
-__device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, int q, bool ok,
-                                     const double *__restrict__ hinv, double wt, double cgrad, int R, double &dir,
-                                     double &exc, HT *__restrict__ Hm, HT *__restrict__ Hp) {
+// The pair's h_p h_q (h = N_g / (g g) per walker pair) is read from the
+// walker array, or passed in already loaded (PairH, for callers that load it
+// ahead of the contraction).
+struct PairH {
+    double hp, hq;
+};
+__device__ inline double pair_h(const double *__restrict__ h, int p, int q) { return h[p] * h[q]; }
+__device__ inline double pair_h(PairH h, int, int) { return h.hp * h.hq; }
+
+template <bool GRAD, typename HT, typename F, typename GT, typename HV>
+__device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, int q, bool ok, HV hinv, double wt,
+                                     double cgrad, int R, double &dir, double &exc, HT *__restrict__ Hm,
+                                     HT *__restrict__ Hp) {
     const int lane = threadIdx.x & 63;
     const int a = (lane & 15) >> 2, b = lane & 3;
 #define GB(G, e, f, i, j) to_cx<F>(G[(4 * (e) + (i)) * ld + 4 * (f) + (j)])
@@ -137,7 +146,7 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
     xt = row16_sum(xt);
     dir = exc = 0.0;
     if (ok) {
-        const double W = hinv[p] * hinv[q] / wt;
+        const double W = pair_h(hinv, p, q) / wt;
         const cx<F> D = cmul(t1, t2);
         dir = -0.5 * (double)D.re * W;
         exc = 0.5 * (double)xt.re * W;

@@ -321,139 +321,146 @@ __device__ inline f4v mfma_pair(u32x4 a, u32x4 b, f4v c) {
                                                       0, 0);
 }
 
-// K chunks reach LDS by direct global -> LDS loads into a ring of three stages
-// (global_load_lds_dwordx4, two chunks ahead, explicit vmcnt waits: the
-// compiler does not track these loads, so it adds no waits of its own before
-// the LDS reads); otherwise by two register stages into two LDS stages.
+// K chunks reach LDS by direct global -> LDS loads (global_load_lds_dwordx4)
+// into a ring of stages, with explicit vmcnt waits: the compiler does not
+// track these loads, so it adds no waits of its own before the LDS reads.
 // The loads take their LDS address in M0, which the assembly sets without
 // declaring it (the compiler does not allocate M0): this relies on the
 // compiled kernels using M0 for nothing else, which a CPU test checks in
 // their AMD assembly (every M0 access is one of these loads or its set-up).
 // The s_nop covers the wait state an M0 write needs before an LDS DMA reads it.
-constexpr bool kBigDma = true;
+//
+// NW = 8: one block of 8 waves per (tau, 128 x 128 tile pair), one block per
+// CU.  NW = 4: the tile pair split into two 128 x 64 halves (the same
+// per-wave tiles), one block of 4 waves each, two blocks per CU, so that one
+// block's epilogue (FP32 / FP64 vector work) runs beside the other's MFMAs.
+template <int NW>
+struct BigCfg {
+    static constexpr int BTB = NW == 8 ? BT : BT / 2;   // B rows (columns of the tile)
+    static constexpr int STAGE = (BT + BTB) * BKW;      // words per stage: A rows then B rows
+    static constexpr int DPC = (BT + BTB) / 8 / NW;     // direct loads per wave and chunk (one 8-row group each)
+    static constexpr int AHEAD = NW == 8 ? 2 : 1;       // chunks in flight beyond the next one
+    static constexpr int NST = AHEAD + 2;               // ring stages
+};
 
-template <typename T, bool GRAD>
-__global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restrict__ U, int Kow, int Ktw,
-                                                        const double *__restrict__ wtau,
-                                                        const double *__restrict__ hinv,
-                                                        const int *__restrict__ tiles16, int n_tp, int n_items, int R,
-                                                        int m, double *__restrict__ partial,
-                                                        uint32_t *__restrict__ Hm, uint32_t *__restrict__ Hp,
-                                                        double cgrad) {
-    constexpr int STAGE = 2 * BT * BKW;  // words per stage: A rows then B rows
-    constexpr int NST = kBigDma ? 3 : 2;
+// waits until at most k chunks (DPC direct loads each) of this wave are in flight
+template <int DPC>
+__device__ inline void wait_dma_chunks(int k) {
+    if (k >= 2)
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * DPC) : "memory");
+    else if (k == 1)
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(DPC) : "memory");
+    else
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+template <typename T, bool GRAD, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void green_big_kernel(
+    const uint32_t *__restrict__ U, int Kow, int Ktw, const double *__restrict__ wtau,
+    const double *__restrict__ hinv, const int *__restrict__ tiles16, int n_tp, int n_items, int R, int m,
+    double *__restrict__ partial, uint32_t *__restrict__ Hm, uint32_t *__restrict__ Hp, double cgrad) {
+    using C = BigCfg<NW>;
+    constexpr int STAGE = C::STAGE, NST = C::NST, DPC = C::DPC, AHEAD = C::AHEAD, WC = NW / 2;
     __shared__ __align__(16) uint32_t lds[NST * STAGE];
     const int per = (n_items + 7) / 8;
     const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (item >= n_items) return;
-    const int t = item / n_tp, tp = item % n_tp;
+    // NW = 4: items 2 i and 2 i + 1 are the two column halves of tile-pair item i
+    const int pair_item = NW == 8 ? item : item >> 1, half = NW == 8 ? 0 : item & 1;
+    const int t = pair_item / n_tp, tp = pair_item % n_tp;
     const int P = tiles16[2 * tp], Q = tiles16[2 * tp + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 2, wc = wave & 3, li = lane & 15, lk = lane >> 4;
+    const int wr = wave / WC, wc = wave % WC, li = lane & 15, lk = lane >> 4;
     const uint32_t *Ut = U + (size_t)t * R * Ktw;
+    const int q0 = BT * Q + C::BTB * half;  // first B row
 
-    // staging unit u = tid + 512 j: row u / 8 of the stage (A: rows of P, B: rows of Q), words 4 (u % 8) .. + 3
-    const uint32_t *src[4];
-    for (int j = 0; j < 4; ++j) {
-        const int u = tid + 512 * j, row = u >> 3;
-        const int grow = row < BT ? BT * P + row : BT * Q + (row - BT);
-        src[j] = Ut + (size_t)min(grow, R - 1) * Ktw + 4 * (u & 7);
-    }
-    // Two register stages: the loads of chunk c + 2 are issued while chunk c
-    // is multiplied and chunk c + 1 (loaded one iteration earlier) goes to LDS.
-    // Past the last chunk the loads re-read it (branch-free, so the waits the
-    // compiler inserts cover only the older stage).
-    u32x4 ra[4], rb[4];
-    auto gload = [&](u32x4(&rg)[4], int w0) __attribute__((always_inline)) {
-        for (int j = 0; j < 4; ++j) rg[j] = *reinterpret_cast<const u32x4 *>(src[j] + w0);
-    };
-    auto lstore = [&](const u32x4(&rg)[4], int buf) __attribute__((always_inline)) {
-        for (int j = 0; j < 4; ++j) {
-            const int u = tid + 512 * j;
-            *reinterpret_cast<u32x4 *>(&lds[buf * STAGE + 4 * swz(u >> 3, u & 7)]) = rg[j];
-        }
-    };
     f4v gm_re[4][2], gm_im[4][2], gp_re[4][2], gp_im[4][2];
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 2; ++j) gm_re[i][j] = gm_im[i][j] = gp_re[i][j] = gp_im[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-    // G(x, y) = sum_k U_x conj(U_y): Re = U_x . U_y, Im = U_x . (-Im U_y, Re U_y)
-    auto chunk = [&](int buf, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
-        const uint32_t *l = &lds[buf * STAGE];
+    // direct loads: wave w fills the 8-row groups g = w + NW j of a stage (A rows of P, then
+    // B rows), one 16-byte unit per lane: row 8 g + lane / 8 at slot lane % 8, i.e. global
+    // unit (lane % 8) ^ (row & 7) (the swizzle of swz)
+    const uint32_t *dsrc[DPC];
 #pragma unroll
-        for (int ks = 0; ks < BKW / 4; ks += 4) {  // 16-byte units: lane group lk reads unit ks + lk
-            u32x4 a[4];
-            for (int i = 0; i < 4; ++i)
-                a[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, ks + lk));
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const u32x4 b = *reinterpret_cast<const u32x4 *>(l + 4 * swz(BT + 32 * wc + 16 * j + li, ks + lk));
-                u32x4 w;
-                for (int q = 0; q < 4; ++q) w[q] = ((b[q] >> 16) | (b[q] << 16)) ^ 0x8000u;
-                for (int i = 0; i < 4; ++i) {
-                    re[i][j] = mfma_pair<T>(a[i], b, re[i][j]);
-                    im[i][j] = mfma_pair<T>(a[i], w, im[i][j]);
-                }
-            }
-        }
-    };
-    // direct loads: wave w fills the 8-row groups g = w + 8 j of a stage (j < 2: rows of P,
-    // j >= 2: rows of Q), one 16-byte unit per lane: row 8 g + lane / 8 at slot lane % 8,
-    // i.e. global unit (lane % 8) ^ (row & 7) (the swizzle of swz)
-    const uint32_t *dsrc[4];
-    for (int j = 0; j < 4; ++j) {
-        const int row = 8 * (wave + 8 * j) + lane / 8, unit = (lane & 7) ^ (row & 7);
-        const int grow = row < BT ? BT * P + row : BT * Q + (row - BT);
+    for (int j = 0; j < DPC; ++j) {
+        const int row = 8 * (wave + NW * j) + lane / 8, unit = (lane & 7) ^ (row & 7);
+        const int grow = row < BT ? BT * P + row : q0 + (row - BT);
         dsrc[j] = Ut + (size_t)min(grow, R - 1) * Ktw + 4 * unit;
     }
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)(&lds[0]);
     auto dma = [&](int w0, int st) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < DPC; ++j) {
             const uint32_t m0v =
-                __builtin_amdgcn_readfirstlane(lds0 + 4u * (uint32_t)(st * STAGE) + 1024u * (uint32_t)(wave + 8 * j));
+                __builtin_amdgcn_readfirstlane(lds0 + 4u * (uint32_t)(st * STAGE) + 1024u * (uint32_t)(wave + NW * j));
             asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v),
                          "v"(dsrc[j] + w0)
                          : "memory");
         }
     };
-    auto stream = [&](int w_lo, int w_hi, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
-        const int n = (w_hi - w_lo) / BKW;
-        if (n == 0) return;
-        if constexpr (kBigDma) {
-            dma(w_lo, 0);
-            if (n > 1) dma(w_lo + BKW, 1);
-            for (int c = 0; c < n; ++c) {
-                // this wave's loads of chunk c are done once at most the four of chunk c + 1 are out
-                if (c + 1 < n)
-                    asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
-                else
-                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                __syncthreads();  // every wave's chunk c is in LDS, every wave is done with chunk c - 1
-                if (c + 2 < n) dma(w_lo + (c + 2) * BKW, (c + 2) % 3);
-                chunk(c % 3, re, im);
+    // G(x, y) = sum_k U_x conj(U_y): Re = U_x . U_y, Im = U_x . (-Im U_y, Re U_y)
+    auto rdf = [&](int st, int s, u32x4(&fa)[4], u32x4(&fb)[2]) __attribute__((always_inline)) {
+        const uint32_t *l = &lds[st * STAGE];  // 16-byte units: lane group lk reads unit 4 s + lk
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            fa[i] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(64 * wr + 16 * i + li, 4 * s + lk));
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            fb[j] = *reinterpret_cast<const u32x4 *>(l + 4 * swz(BT + 32 * wc + 16 * j + li, 4 * s + lk));
+    };
+    auto mmf = [&](const u32x4(&fa)[4], const u32x4(&fb)[2], f4v(&re)[4][2], f4v(&im)[4][2])
+                   __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            u32x4 w;
+            for (int q = 0; q < 4; ++q) w[q] = ((fb[j][q] >> 16) | (fb[j][q] << 16)) ^ 0x8000u;
+            for (int i = 0; i < 4; ++i) {
+                re[i][j] = mfma_pair<T>(fa[i], fb[j], re[i][j]);
+                im[i][j] = mfma_pair<T>(fa[i], w, im[i][j]);
             }
-            __syncthreads();  // the stages are refilled from stage 0 by the next stream / the epilogue
-            return;
-        }
-        auto at = [&](int c) { return w_lo + min(c, n - 1) * BKW; };
-        gload(ra, at(0));
-        gload(rb, at(1));
-        lstore(ra, 0);
-        __syncthreads();
-        for (int c = 0; c < n; c += 2) {
-            gload(ra, at(c + 2));  // rb holds chunk c + 1
-            chunk(0, re, im);
-            if (c + 1 < n) lstore(rb, 1);
-            __syncthreads();
-            if (c + 1 >= n) break;
-            gload(rb, at(c + 3));  // ra holds chunk c + 2
-            chunk(1, re, im);
-            if (c + 2 < n) lstore(ra, 0);
-            __syncthreads();
         }
     };
-    stream(0, Kow, gm_re, gm_im);
-    stream(Kow, Ktw, gp_re, gp_im);
+    // One ring over the G- chunks followed by the G+ chunks (contiguous in K).
+    // Each chunk holds two MFMA K steps whose fragments sit in two register
+    // sets: the barrier that publishes chunk c + 1 comes between chunk c's
+    // two K steps, so chunk c + 1's first fragments are read while chunk c's
+    // second K step multiplies.  The stage refilled after that barrier held
+    // chunk c - 1, whose reads every wave consumed before reaching it.
+    const int nm = Kow / BKW, n = Ktw / BKW;
+    u32x4 fa0[4], fb0[2], fa1[4], fb1[2];
+    // chunk c < n - 1 (the last chunk, below, publishes nothing; a single
+    // path through the step keeps the compiler's LDS-read waits exact)
+    auto step = [&](int c, f4v(&re)[4][2], f4v(&im)[4][2]) __attribute__((always_inline)) {
+        rdf(c % NST, 1, fa1, fb1);
+        __builtin_amdgcn_sched_barrier(0);  // reads issued ahead of the MFMAs that hide them
+        mmf(fa0, fb0, re, im);
+        // this wave's loads of chunk c + 1 are done once only those of later chunks are out
+        wait_dma_chunks<DPC>(min(AHEAD - 1, n - 2 - c));
+        asm volatile("s_barrier" ::: "memory");
+        if (c + AHEAD + 1 < n) dma((c + AHEAD + 1) * BKW, (c + AHEAD + 1) % NST);
+        rdf((c + 1) % NST, 0, fa0, fb0);
+        __builtin_amdgcn_sched_barrier(0);
+        mmf(fa1, fb1, re, im);
+    };
+#pragma unroll
+    for (int c = 0; c <= AHEAD; ++c)
+        if (c < n) dma(c * BKW, c);
+    wait_dma_chunks<DPC>(min(AHEAD, n - 1));
+    asm volatile("s_barrier" ::: "memory");
+    rdf(0, 0, fa0, fb0);
+    for (int c = 0; c < nm; ++c) step(c, gm_re, gm_im);  // nm < n: G+ has at least one chunk
+    for (int c = nm; c < n - 1; ++c) step(c, gp_re, gp_im);
+    // the epilogue's pair weights, loaded once here (in order behind the direct loads):
+    // h of walker rows 8 wr + k of P and of this lane group's column walker
+    double hp[8], hq;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) hp[k] = hinv[min(BW * P + 8 * wr + k, m - 1)];
+    hq = hinv[min(q0 / 8 + 4 * wc + lk, m - 1)];
+    rdf((n - 1) % NST, 1, fa1, fb1);
+    __builtin_amdgcn_sched_barrier(0);
+    mmf(fa0, fb0, gp_re, gp_im);
+    mmf(fa1, fb1, gp_re, gp_im);
+    __syncthreads();  // the epilogue reuses the stages
 
     // epilogue: wave-private G rows in LDS (so wave barriers order the staging
     // and the reads; the K loop ended with a block barrier), 8 rows (one walker) x 32 columns
@@ -480,10 +487,10 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
                         Gp[e] = float2{gp_re[i][j][v], gp_im[i][j][v]};
                     }
             __builtin_amdgcn_wave_barrier();
-            const int p = BW * P + 8 * wr + 2 * i + h, q = BW * Q + 4 * wc + lk;
+            const int p = BW * P + 8 * wr + 2 * i + h, q = q0 / 8 + 4 * wc + lk;
             double dir, exc;
-            contract_pair<GRAD, uint32_t, float>(Gm + 8 * lk, Gp + 8 * lk, GLD, p, q, p < q && q < m, hinv, wt, cgrad,
-                                                 R, dir, exc, Hm_t, Hp_t);
+            contract_pair<GRAD, uint32_t, float>(Gm + 8 * lk, Gp + 8 * lk, GLD, p, q, p < q && q < m,
+                                                 PairH{hp[2 * i + h], hq}, wt, cgrad, R, dir, exc, Hm_t, Hp_t);
             const double d0 = lane_value(dir, 0), d1 = lane_value(dir, 16), d2 = lane_value(dir, 32),
                          d3 = lane_value(dir, 48);
             const double x0 = lane_value(exc, 0), x1 = lane_value(exc, 16), x2 = lane_value(exc, 32),
@@ -493,29 +500,38 @@ __global__ __launch_bounds__(512) void green_big_kernel(const uint32_t *__restri
             __builtin_amdgcn_wave_barrier();
         }
     if (lane == 0) {
-        double *out = partial + ((size_t)item * 8 + wave) * 2;
+        // eight slots per tile pair, slot 4 wr + (column group of four walkers)
+        double *out = partial + ((size_t)pair_item * 8 + 4 * wr + WC * half + wc) * 2;
         out[0] = dsum;
         out[1] = xsum;
     }
 }
 
-template <typename T>
-hipError_t launch_big_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
-    const int n_items = c->n_tp16 * n_tau;
+template <typename T, int NW>
+hipError_t launch_big_nw(const mcmp2_ctx *c, int n_tau, bool grad) {
+    const int n_items = c->n_tp16 * n_tau * (8 / NW);
     const int per = (n_items + 7) / 8;
     const double cgrad = -0.5 / (0.5 * (double)c->m * (double)(c->m - 1) * (double)n_tau);
     const uint32_t *U = reinterpret_cast<const uint32_t *>(c->U);
     uint32_t *Hm = reinterpret_cast<uint32_t *>(c->Hm), *Hp = reinterpret_cast<uint32_t *>(c->Hp);
-    const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
     if (grad)
-        green_big_kernel<T, true><<<8 * per, 512, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau, c->hinv,
-                                                                  c->tiles16, c->n_tp16, n_items, c->R, c->m,
-                                                                  c->partial, Hm, Hp, cgrad);
+        green_big_kernel<T, true, NW><<<8 * per, 64 * NW, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau,
+                                                                        c->hinv, c->tiles16, c->n_tp16, n_items,
+                                                                        c->R, c->m, c->partial, Hm, Hp, cgrad);
     else
-        green_big_kernel<T, false><<<8 * per, 512, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau, c->hinv,
-                                                                   c->tiles16, c->n_tp16, n_items, c->R, c->m,
-                                                                   c->partial, nullptr, nullptr, 0.0);
-    hipError_t e = hipGetLastError();
+        green_big_kernel<T, false, NW><<<8 * per, 64 * NW, 0, c->stream>>>(U, c->Ko / 2, c->Ktot / 2, c->wtau,
+                                                                         c->hinv, c->tiles16, c->n_tp16, n_items,
+                                                                         c->R, c->m, c->partial, nullptr, nullptr,
+                                                                         0.0);
+    return hipGetLastError();
+}
+
+constexpr int kBigWaves = 4;
+
+template <typename T>
+hipError_t launch_big_typed(const mcmp2_ctx *c, int n_tau, bool grad) {
+    const int ps = prof_begin(c, MCMP2_K_GREEN_GEMM);
+    hipError_t e = launch_big_nw<T, kBigWaves>(c, n_tau, grad);
     if (e != hipSuccess) return e;
     return prof_end(c, ps, MCMP2_K_GREEN_GEMM);
 }
