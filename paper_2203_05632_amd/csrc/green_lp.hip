@@ -294,8 +294,9 @@ __global__ __launch_bounds__(256) void green_lp_kernel(const T *__restrict__ U, 
 }
 
 // ---------------------------------------------------------------------------
-// BF16 / FP16 operands, large problems: one block of 8 waves per (tau, tile
-// pair) with 128 x 128 block tiles (16 x 16 walkers), G- and G+ both kept in
+// BF16 / FP16 operands, large problems: (tau, tile pair) items with 128 x 128
+// tiles (16 x 16 walkers), each run by one block of 8 waves or by two blocks
+// of 4 waves (128 x 64 halves; green_big_kernel's NW), G- and G+ both kept in
 // registers (each wave: 64 rows x 32 columns of each).  Work items
 // (tau-major, tile pairs in 4 x 8 patches) are dealt to the XCDs in
 // contiguous ranges (block b runs on XCD b % 8), so that blocks of one XCD
