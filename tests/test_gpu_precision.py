@@ -49,6 +49,9 @@ def _ctx(inp, **kw):
                                              # 273 (tau, 16-walker tile pair) items: the BF16 / FP16 modes take
                                              # the 128x128-tile kernel; m = 200 leaves a half-filled last tile
                                              ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0]),
+                                             # m = 204: the last tile's second 128 x 64 half holds
+                                             # walkers 200-203 of its eight
+                                             ("C1", dict(m=204, n_tau=3), [0.15, 0.6, 2.0]),
                                              # one tau per step: 276 tile pairs of 16 walkers (m = 360, a
                                              # half-filled last tile) still take the 128x128-tile kernel
                                              ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4]),
@@ -176,6 +179,7 @@ def test_systematic_error_below_one_percent_of_sigma_precision_workload(chain_ru
 @pytest.mark.parametrize("name,over,taus", [("C1", dict(), [0.3, 1.0]),
                                              ("C0", dict(m=13, n_occ=6, n_vir=10, n_tau=3), [0.2, 0.7, 2.5]),
                                              ("C1", dict(m=200, n_tau=3), [0.15, 0.6, 2.0]),
+                                             ("C1", dict(m=204, n_tau=3), [0.15, 0.6, 2.0]),
                                              ("C0", dict(m=360, n_occ=6, n_vir=10, n_tau=1), [0.4]),
                                              ("C1", dict(m=720, n_tau=1), [0.5])])
 def test_low_precision_gradients_near_fp64(prec, name, over, taus):
