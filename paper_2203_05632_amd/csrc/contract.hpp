@@ -126,10 +126,19 @@ struct PairH {
 __device__ inline double pair_h(const double *__restrict__ h, int p, int q) { return h[p] * h[q]; }
 __device__ inline double pair_h(PairH h, int, int) { return h.hp * h.hq; }
 
+// A pair's six adjoint block elements (lane (a, b): element [a][b] of H-(1,3),
+// H-(2,4), H+(1,3), H+(2,4), H+(1,4), H+(2,3)) and their scale c (the last
+// two take -c), for callers that store them themselves.
+template <typename F>
+struct AdjVals {
+    cx<F> m13, m24, p13, p24, p14, p23;
+    double cw;
+};
+
 template <bool GRAD, typename HT, typename F, typename GT, typename HV>
 __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, int q, bool ok, HV hinv, double wt,
                                      double cgrad, int R, double &dir, double &exc, HT *__restrict__ Hm,
-                                     HT *__restrict__ Hp) {
+                                     HT *__restrict__ Hp, AdjVals<F> *adj = nullptr) {
     const int lane = threadIdx.x & 63;
     const int a = (lane & 15) >> 2, b = lane & 3;
 #define GB(G, e, f, i, j) to_cx<F>(G[(4 * (e) + (i)) * ld + 4 * (f) + (j)])
@@ -197,12 +206,18 @@ __device__ inline void contract_pair(const GT *Gm, const GT *Gp, int ld, int p, 
                     h_store(H, cc * R + r, re, -im);
                 }
             };
-            put(Hm, r1, c3, csub(cmul(t2, p13), s13), cw);
-            put(Hm, r2, c4, csub(cmul(t1, p24), s24), cw);
-            put(Hp, r1, c3, cmul(conjc(t2), a13), cw);
-            put(Hp, r2, c4, cmul(conjc(t1), a24), cw);
-            put(Hp, r1, c4, s14, -cw);
-            put(Hp, r2, c3, s23, -cw);
+            const cx<F> h13 = csub(cmul(t2, p13), s13), h24 = csub(cmul(t1, p24), s24);
+            const cx<F> g13 = cmul(conjc(t2), a13), g24 = cmul(conjc(t1), a24);
+            if (adj) {
+                *adj = AdjVals<F>{h13, h24, g13, g24, s14, s23, cw};
+            } else {
+                put(Hm, r1, c3, h13, cw);
+                put(Hm, r2, c4, h24, cw);
+                put(Hp, r1, c3, g13, cw);
+                put(Hp, r2, c4, g24, cw);
+                put(Hp, r1, c4, s14, -cw);
+                put(Hp, r2, c3, s23, -cw);
+            }
         }
     }
 #undef GB

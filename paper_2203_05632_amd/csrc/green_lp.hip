@@ -468,38 +468,99 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // (four walkers) at a time.  Rows are padded to 36 complex (288 B, i.e.
     // 32 B apart modulo the 256-byte bank row), so the 4-row reads of the
     // contraction hit each bank at most twice.
-    constexpr int GLD = 36;
-    float2 *Gm = reinterpret_cast<float2 *>(lds) + wave * 1024;
+    constexpr int GLD = 36, WST = 1920;  // float2 per wave's staging slot (15 KB)
+    float2 *Gm = reinterpret_cast<float2 *>(lds) + wave * WST;
     float2 *Gp = Gm + 8 * GLD;
     uint32_t *Hm_t = GRAD ? Hm + (size_t)t * R * R : nullptr;
     uint32_t *Hp_t = GRAD ? Hp + (size_t)t * R * R : nullptr;
     const double wt = wtau[t];
     double dsum = 0.0, xsum = 0.0;
-#pragma unroll  // constant indices keep the accumulators in registers
-    for (int i = 0; i < 4; ++i)
+    // With gradients, when every walker pair of the block counts (p < q < m),
+    // the adjoint blocks are staged in the wave's LDS slot and stored in whole
+    // 128-byte rows: D (8 x 32) the rows of walker p x the wave's 32 columns,
+    // T (32 x 32) their Hermitian partners for four walkers p at a time.  H-'s
+    // (1,4) / (2,3) blocks, which are zero, stay zero in Dm / Tm and are stored
+    // with the rest.  Otherwise each element and its partner are stored apart.
+    const int qb = q0 / 8 + 4 * wc;  // first column walker of the wave
+    const bool staged = GRAD && P < Q && q0 / 8 + C::BTB / 8 <= m;
+    uint32_t *Dm = reinterpret_cast<uint32_t *>(Gp + 8 * GLD), *Dp = Dm + 256, *Tm = Dp + 256, *Tp = Tm + 1024;
+    if (staged) {
+        *reinterpret_cast<u32x4 *>(Dm + 4 * lane) = u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // MFMA result rows 4 lk + v of sub-tile i: walker row h holds lane groups lk = 2 h, 2 h + 1
-            if ((lk >> 1) == h)
-                for (int j = 0; j < 2; ++j)
-                    for (int v = 0; v < 4; ++v) {
-                        const int e = (4 * (lk & 1) + v) * GLD + 16 * j + li;
-                        Gm[e] = float2{gm_re[i][j][v], gm_im[i][j][v]};
-                        Gp[e] = float2{gp_re[i][j][v], gp_im[i][j][v]};
+        for (int j = 0; j < 4; ++j) *reinterpret_cast<u32x4 *>(Tm + 4 * (lane + 64 * j)) = u32x4{0u, 0u, 0u, 0u};
+    }
+    // the pair loop, compiled once per way of storing the adjoint blocks
+    auto pairs = [&](auto st) __attribute__((always_inline)) {
+        constexpr bool ST = decltype(st)::value;
+#pragma unroll  // constant indices keep the accumulators in registers
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                // MFMA result rows 4 lk + v of sub-tile i: walker row h holds lane groups lk = 2 h, 2 h + 1
+                if ((lk >> 1) == h)
+                    for (int j = 0; j < 2; ++j)
+                        for (int v = 0; v < 4; ++v) {
+                            const int e = (4 * (lk & 1) + v) * GLD + 16 * j + li;
+                            Gm[e] = float2{gm_re[i][j][v], gm_im[i][j][v]};
+                            Gp[e] = float2{gp_re[i][j][v], gp_im[i][j][v]};
+                        }
+                __builtin_amdgcn_wave_barrier();
+                const int p = BW * P + 8 * wr + 2 * i + h, q = qb + lk;
+                double dir, exc;
+                AdjVals<float> av;
+                contract_pair<GRAD, uint32_t, float>(Gm + 8 * lk, Gp + 8 * lk, GLD, p, q, p < q && q < m,
+                                                     PairH{hp[2 * i + h], hq}, wt, cgrad, R, dir, exc,
+                                                     ST ? nullptr : Hm_t, ST ? nullptr : Hp_t, ST ? &av : nullptr);
+                if constexpr (ST) {
+                    // element (8 p + dr, 8 qb + dc) into D, its partner (8 qb + dc, 8 pb + tc + dr) into T
+                    // (Dt, Tt: Dm / Tm or Dp / Tp),
+                    // scaled and rounded as the direct stores are
+                    const int a = (lane & 15) >> 2, b = lane & 3, tc = 8 * ((2 * i + h) & 3);
+                    auto sput = [&](uint32_t *Dt, uint32_t *Tt, int dr, int dc, cx<float> v, double scale)
+                                    __attribute__((always_inline)) {
+                        const float sc = (float)scale, re = v.re * sc, im = v.im * sc;
+                        Dt[dr * 32 + dc] = bf16_pair(re, im);
+                        Tt[dc * 32 + tc + dr] = bf16_pair(re, -im);
+                    };
+                    sput(Dm, Tm, a, 8 * lk + b, av.m13, av.cw);
+                    sput(Dm, Tm, 4 + a, 8 * lk + 4 + b, av.m24, av.cw);
+                    sput(Dp, Tp, a, 8 * lk + b, av.p13, av.cw);
+                    sput(Dp, Tp, 4 + a, 8 * lk + 4 + b, av.p24, av.cw);
+                    sput(Dp, Tp, a, 8 * lk + 4 + b, av.p14, -av.cw);
+                    sput(Dp, Tp, 4 + a, 8 * lk + b, av.p23, -av.cw);
+                    __builtin_amdgcn_wave_barrier();
+                    {  // D: lane l stores row l / 8, 16-byte unit l % 8
+                        const int row = lane >> 3, u = lane & 7;
+                        const size_t g = (size_t)(8 * p + row) * R + 8 * qb + 4 * u;
+                        *reinterpret_cast<u32x4 *>(Hm_t + g) = *reinterpret_cast<const u32x4 *>(Dm + row * 32 + 4 * u);
+                        *reinterpret_cast<u32x4 *>(Hp_t + g) = *reinterpret_cast<const u32x4 *>(Dp + row * 32 + 4 * u);
                     }
-            __builtin_amdgcn_wave_barrier();
-            const int p = BW * P + 8 * wr + 2 * i + h, q = q0 / 8 + 4 * wc + lk;
-            double dir, exc;
-            contract_pair<GRAD, uint32_t, float>(Gm + 8 * lk, Gp + 8 * lk, GLD, p, q, p < q && q < m,
-                                                 PairH{hp[2 * i + h], hq}, wt, cgrad, R, dir, exc, Hm_t, Hp_t);
-            const double d0 = lane_value(dir, 0), d1 = lane_value(dir, 16), d2 = lane_value(dir, 32),
-                         d3 = lane_value(dir, 48);
-            const double x0 = lane_value(exc, 0), x1 = lane_value(exc, 16), x2 = lane_value(exc, 32),
-                         x3 = lane_value(exc, 48);
-            dsum += ((d0 + d1) + d2) + d3;
-            xsum += ((x0 + x1) + x2) + x3;
-            __builtin_amdgcn_wave_barrier();
-        }
+                    if ((i & 1) && h == 1) {  // T complete for walkers pb .. pb + 3
+                        const int pb = BW * P + 8 * wr + 4 * (i >> 1);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int row = 8 * j + (lane >> 3), u = lane & 7;
+                            const size_t g = (size_t)(8 * qb + row) * R + 8 * pb + 4 * u;
+                            *reinterpret_cast<u32x4 *>(Hm_t + g) =
+                                *reinterpret_cast<const u32x4 *>(Tm + row * 32 + 4 * u);
+                            *reinterpret_cast<u32x4 *>(Hp_t + g) =
+                                *reinterpret_cast<const u32x4 *>(Tp + row * 32 + 4 * u);
+                        }
+                    }
+                }
+                const double d0 = lane_value(dir, 0), d1 = lane_value(dir, 16), d2 = lane_value(dir, 32),
+                             d3 = lane_value(dir, 48);
+                const double x0 = lane_value(exc, 0), x1 = lane_value(exc, 16), x2 = lane_value(exc, 32),
+                             x3 = lane_value(exc, 48);
+                dsum += ((d0 + d1) + d2) + d3;
+                xsum += ((x0 + x1) + x2) + x3;
+                __builtin_amdgcn_wave_barrier();
+            }
+    };
+    if (staged)
+        pairs(std::true_type());
+    else
+        pairs(std::false_type());
     if (lane == 0) {
         // eight slots per tile pair, slot 4 wr + (column group of four walkers)
         double *out = partial + ((size_t)pair_item * 8 + 4 * wr + WC * half + wc) * 2;
