@@ -588,6 +588,9 @@ hipError_t launch_big_nw(const mcmp2_ctx *c, int n_tau, bool grad) {
     return hipGetLastError();
 }
 
+// Block shape of the large-problem kernel: 4 (two 4-wave half-tile blocks per
+// tile pair, two per CU; measured faster at 512 walker pairs) or 8 (one 8-wave
+// block per tile pair); both give the same results bit for bit.
 constexpr int kBigWaves = 4;
 
 template <typename T>
